@@ -1,0 +1,175 @@
+"""Throughput benchmark: Mpixel/s unwrapped at 1e-6 relative residual.
+
+One step = one lp_unwrap_batch call over the uneven batch workload (256
+random-Gaussian maps, sides drawn from {128,256,384,512,768,1024}, noise
+sigma ~ U[0.1, 0.8] rad, p = 0, tau = 0.01, 10 outer iterations, DCT
+preconditioner, mixed precision with split-bf16 MFMA transforms), with every
+psi already resident in HBM when the timed region starts.
+
+Prints one JSON line (rank 0) with the metric, the roofline of the dominant
+kernel (achieved = algorithmic bytes or flops of its launches / their summed
+HIP-event durations, measured on the library's stream inside the timed
+region), the plain-FP64 sequential comparison and the oracle's CPU rate on a
+bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+PEAK_BF16_TFLOPS = 2500.0
+PEAK_FP16_TFLOPS = 2500.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--maps", type=int, default=256)
+    ap.add_argument("--outer", type=int, default=10)
+    ap.add_argument("--dct-mode", default="split_bf16")
+    ap.add_argument("--fp64-compare", type=int, default=1,
+                    help="also time the plain FP64 sequential loop once (0: skip)")
+    ap.add_argument("--cpu-baseline", type=int, default=1)
+    ap.add_argument("--profile", action="store_true", help="fewer steps, no extras (for rocprof)")
+    return ap.parse_args()
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
+              "(the batch shards across GPUs by map, see the design notes)" % a.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2203_13675_amd import synth
+    from paper_2203_13675_amd.binding import Context, default_options, KERNEL_CLASSES
+
+    shapes = synth.batch_sizes(a.maps, seed=3000)
+    maps = synth.batch_maps(a.maps, seed=3000)
+    total_px = sum(m * n for m, n in shapes)
+    dev = torch.device("cuda:0")
+    psis = [torch.from_numpy(p).to(dev) for p, _ in maps]
+    phis = [torch.zeros_like(t) for t in psis]
+    opts = dict(p=0.0, eps=0.01, preconditioner="dct", tol=1e-6)
+    ctx = Context(0)
+    o = default_options(precision="mixed", dct_mode=a.dct_mode, k_max=a.outer, outer_tol=0.0)
+
+    def step():
+        return ctx.batch(psis, phis=phis, options=o, **opts)
+
+    # warm-up with every kernel class timed: find the dominant class
+    ctx.kernel_timing("all")
+    for _ in range(max(1, a.warmup)):
+        step()
+    torch.cuda.synchronize()
+    warm = ctx.kernel_timing_report()
+    dominant = max(warm.items(), key=lambda kv: kv[1]["ms"])[0] if warm else "spmv"
+    # timed region: only the dominant class carries events
+    ctx.kernel_timing(dominant)
+    t0 = time.perf_counter()
+    stats = None
+    for _ in range(a.steps):
+        _, rc, stats = step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / a.steps
+    ktimes = ctx.kernel_timing_report()
+    ctx.kernel_timing("off")
+    warm_split = {k: v["ms"] / max(1, a.warmup) for k, v in warm.items()}
+
+    value = total_px / dt / 1e6
+    inner = sum(s["inner_iters_total"] for s in stats)
+    worst_relres = max(s["final_relres"] for s in stats)
+
+    # dominant kernel class by summed time
+    dom = max(ktimes.items(), key=lambda kv: kv[1]["ms"]) if ktimes else None
+    roofline = None
+    if dom:
+        name, kt = dom
+        per_launch_s = kt["ms"] / 1e3 / max(kt["launches"], 1)
+        if kt["flops"] > 0 and name.startswith("dct"):
+            ach = kt["flops"] / max(kt["launches"], 1) / per_launch_s / 1e12
+            roofline = {"bound": "mfma", "kernel": name, "achieved": ach,
+                        "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                        "frac": ach / PEAK_BF16_TFLOPS, "traffic": None,
+                        "avg_launch_us": per_launch_s * 1e6, "launches": kt["launches"]}
+        else:
+            ach = kt["bytes"] / max(kt["launches"], 1) / per_launch_s / 1e9
+            roofline = {"bound": "hbm", "kernel": name, "achieved": ach, "peak": PEAK_HBM_GBS,
+                        "unit": "GB/s", "frac": ach / PEAK_HBM_GBS, "traffic": None,
+                        "avg_launch_us": per_launch_s * 1e6, "launches": kt["launches"]}
+
+    out = {
+        "metric": "Mpixel/s unwrapped at 1e-6 rel. residual; batched mixed-prec vs plain FP64",
+        "value": value, "unit": "Mpixel/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batch of %d uneven random-Gaussian maps (sides in "
+                               "{128..1024}), p=0, tau=0.01, %d outer iterations, DCT "
+                               "preconditioner, relres 1e-6" % (a.maps, a.outer),
+                   "maps": a.maps, "total_pixels": total_px, "outer_iters": a.outer,
+                   "precision": "mixed: f32 CG vectors, %s DCT on MFMA, f64 dots and "
+                                "residual refinement" % a.dct_mode},
+        "pcg_iters_per_step": inner, "cg_iters_per_s": inner / dt,
+        "worst_final_relres": worst_relres,
+        "kernel_ms_per_step_warmup": warm_split,
+        "roofline": roofline,
+    }
+
+    if a.fp64_compare and not a.profile:
+        t0 = time.perf_counter()
+        o64 = default_options(precision="fp64", k_max=a.outer, outer_tol=0.0)
+        for ps, ph in zip(psis, phis):
+            ctx.solve(ps, phi=ph, options=o64, **opts)
+        torch.cuda.synchronize()
+        t64 = time.perf_counter() - t0
+        out["fp64_sequential"] = {"value": total_px / t64 / 1e6, "unit": "Mpixel/s",
+                                  "seconds": t64}
+        out["speedup_vs_fp64_sequential"] = out["value"] / out["fp64_sequential"]["value"]
+
+    if a.cpu_baseline and not a.profile:
+        out["cpu_baseline"] = cpu_baseline(maps, shapes, a.outer)
+    ctx.close()
+    print(json.dumps(out))
+
+
+def cpu_baseline(maps, shapes, outer):
+    """The oracle (FP64 numpy + C helper) on a bounded sample of the batch: the
+    first maps until ~15 s of CPU work, same settings.  Reports Mpixel/s."""
+    from oracle import lp_oracle
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        threads = 1
+    t0 = time.perf_counter()
+    px = 0
+    used = []
+    for (psi, _), (M, N) in zip(maps, shapes):
+        if M * N > 256 * 384:
+            continue
+        lp_oracle.unwrap(psi, p=0.0, tau=0.01, precond="dct", tol=1e-6, k_max=outer,
+                         outer_tol=0.0)
+        px += M * N
+        used.append("%dx%d" % (M, N))
+        if time.perf_counter() - t0 > 15.0:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": px / dt / 1e6, "unit": "Mpixel/s", "cores": threads, "kind": "oracle",
+            "sample": "%d maps of the batch (%s), same settings, %.1f s" % (len(used),
+                                                                           ",".join(used), dt)}
+
+
+if __name__ == "__main__":
+    main()

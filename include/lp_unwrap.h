@@ -1,0 +1,248 @@
+/*
+ * lp_unwrap -- L^p-norm phase unwrapping on one AMD Instinct MI355X (gfx950).
+ *
+ * The method (Legarda-Saenz, Brito-Loeza, Espinosa-Romero, "On the
+ * performance of preconditioned methods to solve L^p-norm phase unwrapping",
+ * arXiv 2203.13675):
+ *
+ *   Section 2, Eq. (2): minimise sum |grad phi - W(grad psi)|^p over the
+ *   unwrapped phase phi, given the wrapped phase psi (Eq. (1)).
+ *   Section 2.1, Eqs. (4)-(7): finite differences turn the Euler-Lagrange
+ *   equation into A(U,V) phi = b, a weighted five-point Neumann Laplacian with
+ *   weights U, V (Eq. (6)) that depend on phi.
+ *   Algorithm 1: fixed-point loop -- recompute U, V from phi^k, solve the
+ *   linear system with preconditioned CG (warm start phi^k), repeat.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  * Maps are M rows x N columns, row-major, contiguous (element (i, j) at
+ *    i*N + j).  "x" differences run along j (contiguous), "y" along i.
+ *  * Every array argument is a DEVICE pointer on the context's device, owned
+ *    by the caller, that must stay valid until the call returns.  Calls are
+ *    ordered on the context's stream and return only after the work they
+ *    enqueue has completed (they read device status words).
+ *  * A context is not thread-safe: use one context per host thread / stream.
+ *  * Functions return an lpu_status; a negative value is an error and the
+ *    outputs are unspecified.  lp_unwrap_last_error() describes the most
+ *    recent error on a context.
+ *  * Precision LPU_FP64: every vector, weight and reduction in double.
+ *    Precision LPU_MIXED: weights and CG vectors in float, inner products
+ *    accumulated in double, the outer residual b - A phi and the solution phi
+ *    in double (iterative refinement).
+ */
+#ifndef LP_UNWRAP_H
+#define LP_UNWRAP_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lp_unwrap_ctx lp_unwrap_ctx;
+
+/* Status codes. */
+enum lpu_status {
+    LPU_OK = 0,                /* converged (stop rule met)                       */
+    LPU_NOT_CONVERGED = 1,     /* a cap (k_max, l_max, max_refine) was hit; the
+                                  output phi is valid                              */
+    LPU_ERR_INVALID_ARG = -1,  /* null pointer, empty map, p outside [0,2],
+                                  tau <= 0, tol < 0, unknown preconditioner ...    */
+    LPU_ERR_OOM = -2,          /* device allocation failed                        */
+    LPU_ERR_HIP = -3,          /* HIP runtime error (message in last_error)       */
+    LPU_ERR_NONFINITE = -4,    /* psi or the mask holds NaN/Inf                   */
+    LPU_ERR_BREAKDOWN = -5     /* PCG breakdown: d^T A d <= 0 or a non-finite
+                                  alpha/beta/delta                                 */
+};
+
+/* The preconditioners M of Section 2.1's list (I, D, ILU(0), IC(0), SOR) and
+ * the DCT fast-Poisson preconditioner (M = unit-weight Neumann Laplacian). */
+enum lpu_preconditioner {
+    LPU_PC_NONE = 0,    /* M = I: plain CG                                      */
+    LPU_PC_JACOBI = 1,  /* M = diag(A)                                          */
+    LPU_PC_ILU0 = 2,    /* incomplete LU, no fill-in, natural row-major order    */
+    LPU_PC_IC0 = 3,     /* incomplete Cholesky, no fill-in; for this symmetric
+                           five-point matrix it equals ILU(0)                    */
+    LPU_PC_SSOR = 4,    /* symmetric SOR with relaxation ssor_omega              */
+    LPU_PC_DCT = 5      /* DCT-II/III Poisson solve, zero mode dropped           */
+};
+
+enum lpu_stop_rule {
+    LPU_STOP_RELRES = 0, /* ||b - A phi|| <= tol ||b||, confirmed on the true residual */
+    LPU_STOP_PAPER = 1   /* delta_new <= eps_cg^2 delta_0 (Algorithm 1's inner test)   */
+};
+
+enum lpu_precision { LPU_FP64 = 0, LPU_MIXED = 1 };
+
+/* Arithmetic of the DCT transforms in the MIXED path (FP64 path: always FP64). */
+enum lpu_dct_mode {
+    LPU_DCT_FP32 = 0,        /* FP32 FMA GEMMs                                   */
+    LPU_DCT_SPLIT_BF16 = 1,  /* bf16 hi/lo split, 3 MFMA products, FP32 accumulate */
+    LPU_DCT_FP16_SCALED = 2  /* power-of-two scaled fp16, 1 MFMA product, FP32 acc */
+};
+
+typedef struct lpu_options {
+    int k_max;             /* outer iterations cap (default 500, Section 3)            */
+    double outer_tol;      /* outer relative-change tolerance (default 1e-6, Section 3);
+                              <= 0: run exactly k_max outer iterations                  */
+    long long l_max;       /* inner iterations cap per solve; <= 0: 2*M*N (Section 3)   */
+    int stop_rule;         /* lpu_stop_rule (default LPU_STOP_RELRES)                   */
+    double eps_cg;         /* epsilon of LPU_STOP_PAPER (default 0.005, Section 3)      */
+    int residual_period;   /* true-residual replacement period; <= 0: floor(sqrt(MN))  */
+    double ssor_omega;     /* SSOR relaxation in (0, 2) (default 1)                     */
+    int precision;         /* lpu_precision (default LPU_MIXED)                         */
+    int dct_mode;          /* lpu_dct_mode (default LPU_DCT_SPLIT_BF16)                 */
+    int use_phi0;          /* 1: phi holds the start value on entry; 0: start at 0      */
+    double refine_eta;     /* MIXED: relative residual reduction asked of each FP32
+                              inner solve (default 1e-3)                               */
+    int max_refine;        /* MIXED: refinement steps cap per outer iteration (default 30) */
+} lpu_options;
+
+typedef struct lpu_stats {
+    int outer_iters;             /* outer iterations run                              */
+    long long inner_iters_total; /* PCG iterations summed over all inner solves       */
+    int refinements;             /* MIXED: FP32 inner solves run (FP64: = outer_iters) */
+    double final_relres;         /* ||b - A phi|| / ||b|| of the last system, in FP64  */
+    double outer_err;            /* last ||phi^{k+1} - phi^k|| / ||phi^k|| (inf at 0)   */
+    double setup_ms;             /* time building U, V, b and M                        */
+    double solve_ms;             /* wall time of the whole call                        */
+    int converged;               /* 1 when the call returns LPU_OK                     */
+    int status;                  /* status of this map                                 */
+} lpu_stats;
+
+/* One map of a batch (all pointers device pointers, see conventions). */
+typedef struct lpu_map {
+    int rows, cols;        /* M, N                                                 */
+    const double* psi;     /* wrapped phase, M*N doubles in (-pi, pi]               */
+    const float* mask;     /* quality in [0,1], M*N floats, or NULL (all ones)      */
+    double* phi;           /* output unwrapped phase, M*N doubles (input: phi0)     */
+} lpu_map;
+
+/* Fill *opt with the defaults listed above. */
+void lpu_default_options(lpu_options* opt);
+
+/* Create a context bound to HIP device `device` and stream `stream` (a
+ * hipStream_t; NULL = the null stream).  Workspace for maps of up to
+ * max_rows x max_cols is allocated now (0, 0: allocate on first use); larger
+ * maps grow it.  The context owns its workspace; free it with
+ * lp_unwrap_destroy.  Errors: LPU_ERR_INVALID_ARG, LPU_ERR_OOM, LPU_ERR_HIP. */
+int lp_unwrap_create(lp_unwrap_ctx** out, int device, void* stream, int max_rows, int max_cols);
+
+/* Destroy a context and free its device memory.  NULL is ignored. */
+void lp_unwrap_destroy(lp_unwrap_ctx* ctx);
+
+/* Unwrap one map: Algorithm 1 with the chosen preconditioner.
+ *   psi      [in]  M*N doubles, the wrapped phase of Eq. (1).
+ *   mask     [in]  M*N floats in [0,1] or NULL.  Edge quality is
+ *                  min(mask_a, mask_b) and multiplies the weights U, V of
+ *                  Eq. (6).  Pixels with no weighted edge keep phi0.
+ *   p        L^p exponent of Eq. (2), 0 <= p <= 2.
+ *   eps      tau of Eq. (6) (> 0; the paper uses 0.01).
+ *   preconditioner  lpu_preconditioner.
+ *   tol      inner stop tolerance: relative residual of each linear system
+ *            (LPU_STOP_RELRES) -- the target the outer loop also uses for the
+ *            FP64 residual in the MIXED path.
+ *   opts     NULL for lpu_default_options.
+ *   phi      [in/out] M*N doubles.
+ *   stats    [out] may be NULL.
+ * Returns LPU_OK, LPU_NOT_CONVERGED or an error (see lpu_status). */
+int lp_unwrap_solve(lp_unwrap_ctx* ctx, int M, int N, const double* psi, const float* mask,
+                    double p, double eps, int preconditioner, double tol,
+                    const lpu_options* opts, double* phi, lpu_stats* stats);
+
+/* Unwrap n_maps independent maps of possibly different sizes together.
+ * `maps` is a HOST array of n_maps descriptors whose pointers are device
+ * pointers.  Every map runs Algorithm 1 with the same p, eps, preconditioner,
+ * tol and options; each map stops on its own (per-map convergence flags), and
+ * every step of every iteration is one launch for all active maps.
+ * Supported preconditioners: LPU_PC_NONE, LPU_PC_JACOBI, LPU_PC_DCT.
+ * per_map: HOST array of n_maps lpu_stats, or NULL.
+ * Returns the worst status over the maps (an error if any map failed). */
+int lp_unwrap_batch(lp_unwrap_ctx* ctx, int n_maps, const lpu_map* maps, double p, double eps,
+                    int preconditioner, double tol, const lpu_options* opts, lpu_stats* per_map);
+
+/* Text for a status code; never NULL. */
+const char* lp_unwrap_status_string(int status);
+
+/* Description of the last error on ctx (empty string if none); never NULL. */
+const char* lp_unwrap_last_error(const lp_unwrap_ctx* ctx);
+
+/* ----------------------------------------------------------------------------
+ * Single steps of the path, exposed so each kernel can be checked on its own.
+ * They run exactly the kernels the solver runs.  `precision` selects the
+ * element type of the weight/vector arguments typed void*: float for
+ * LPU_MIXED, double for LPU_FP64.
+ * ------------------------------------------------------------------------- */
+
+/* Section 2.1: Delta^x_{i,j} = W(psi_{i,j+1} - psi_{i,j}) for j < N-1 and
+ * Delta^y_{i,j} = W(psi_{i+1,j} - psi_{i,j}) for i < M-1, with
+ * W(x) = x - 2 pi ceil((x - pi) / (2 pi)) in (-pi, pi] (Eq. (1) range),
+ * evaluated in FP64.  dx's last column and dy's last row are written as 0.
+ * psi, dx, dy: M*N doubles. */
+int lpu_wrapped_differences(lp_unwrap_ctx* ctx, int M, int N, const double* psi,
+                            double* dx, double* dy);
+
+/* Eq. (6): U_{i,j} = w^x_{i,j} tau / (|phi_{i,j+1} - phi_{i,j} - Delta^x_{i,j}|^(2-p) + tau)
+ * for j < N-1 and 0 on the last column; V likewise along i with 0 on the last
+ * row.  w is the edge quality min(mask_a, mask_b) (1 without a mask).
+ * phi, dx, dy: M*N doubles; mask: M*N floats or NULL; U, V: M*N elements of
+ * the precision's type. */
+int lpu_weights(lp_unwrap_ctx* ctx, int M, int N, int precision, const double* phi,
+                const double* dx, const double* dy, const float* mask, double p, double tau,
+                void* U, void* V);
+
+/* Eq. (7), left side: y = A(U,V) x for every pixel.  U, V, x, y: M*N elements. */
+int lpu_apply_A(lp_unwrap_ctx* ctx, int M, int N, int precision, const void* U, const void* V,
+                const void* x, void* y);
+
+/* Eq. (7), right side: b = Delta^x_{i,j-1}U_{i,j-1} - Delta^x_{i,j}U_{i,j}
+ * + Delta^y_{i-1,j}V_{i-1,j} - Delta^y_{i,j}V_{i,j}, computed in FP64 from
+ * the stored weights.  b: M*N doubles. */
+int lpu_rhs(lp_unwrap_ctx* ctx, int M, int N, int precision, const void* U, const void* V,
+            const double* dx, const double* dy, double* b);
+
+/* s = M^{-1} r for the preconditioner built from U, V (Section 2.1's list
+ * and the DCT Poisson solve); zero on pixels with no weighted edge.
+ * dct_mode applies to LPU_MIXED only.  U, V, r, s: M*N elements. */
+int lpu_precond_apply(lp_unwrap_ctx* ctx, int M, int N, int precision, int preconditioner,
+                      int dct_mode, double omega, const void* U, const void* V,
+                      const void* r, void* s);
+
+/* ILU(0) = IC(0) pivots of A(U,V) in natural order: the diagonal of the
+ * no-fill factor, d_{i,j} = a_{i,j} - U_{i,j-1}^2/d_{i,j-1} - V_{i-1,j}^2/d_{i-1,j},
+ * a pivot below 1e-4 a_{i,j} replaced by a_{i,j}; 1 on isolated pixels.
+ * U, V, piv: M*N elements. */
+int lpu_ilu_pivots(lp_unwrap_ctx* ctx, int M, int N, int precision, const void* U,
+                   const void* V, void* piv);
+
+/* ----------------------------------------------------------------------------
+ * Instrumentation (tracing).  Kernel classes of the path: */
+enum lpu_kernel_class {
+    LPU_KC_SPMV = 0,     /* direction update + q = A d + d^T q           */
+    LPU_KC_UPDATE = 1,   /* x, r updates, pointwise preconditioner, dots  */
+    LPU_KC_CONFIRM = 2,  /* true-residual confirmation                     */
+    LPU_KC_INIT = 3,     /* r0 = b - A x0                                  */
+    LPU_KC_DCT = 4,      /* one DCT contraction stage                      */
+    LPU_KC_SWEEP = 5,    /* ILU/IC/SSOR forward+backward sweeps            */
+    LPU_KC_SETUP = 6,    /* weights, b, preconditioner set-up, refinement  */
+    LPU_KC_COUNT = 7
+};
+
+/* Time every launch of the kernel classes whose bit (1 << class) is set in
+ * class_mask with HIP events recorded on the context's stream (0: off; the
+ * events add a little host work per launch).  Resets the accumulators. */
+int lpu_kernel_timing(lp_unwrap_ctx* ctx, unsigned int class_mask);
+
+/* Accumulated figures of one class since the last lpu_kernel_timing call:
+ * summed event durations (ms), number of launches, and the algorithmic bytes
+ * moved and flops executed by those launches (from the launch shapes: the
+ * bytes each kernel must read and write once, the contraction's multiply-adds
+ * x 2 x products per element for MFMA stages).  Any output may be NULL. */
+int lpu_kernel_timing_get(lp_unwrap_ctx* ctx, int kernel_class, double* total_ms,
+                          long long* launches, double* alg_bytes, double* alg_flops);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LP_UNWRAP_H */

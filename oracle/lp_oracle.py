@@ -367,10 +367,12 @@ def pcg(U, V, b, x0, M: Preconditioner, *, stop_rule: str = "relres", tol: float
     """Solve A x = b (Eq. (7)) by PCG, following the inner loop of Algorithm 1.
 
     stop_rule "paper": run while delta_new > eps_cg^2 * delta_0.
-    stop_rule "relres": run while ||r|| > tol * ||b||; when the recursive residual
-    meets the bound, the true residual b - A x replaces it and is tested again.
-    The true residual replaces the recursive one whenever l is a multiple of
-    ``period`` (default floor(sqrt(MN))), l = 0 included."""
+    stop_rule "relres": run while ||r|| > tol * ||b||, always tested on a true
+    residual: in an iteration where the recursively updated residual first
+    meets the bound, b - A x replaces it (exactly as the periodic replacement
+    does) before the test.  The true residual replaces the recursive one
+    whenever l is a multiple of ``period`` (default floor(sqrt(MN))), l = 0
+    included."""
     Mr, Nc = b.shape
     n = Mr * Nc
     if l_max is None:
@@ -384,22 +386,19 @@ def pcg(U, V, b, x0, M: Preconditioner, *, stop_rule: str = "relres", tol: float
     delta_new = float(np.sum(r * d))
     delta0 = delta_new
     hist = []
-
-    def done(rvec, dn):
-        if stop_rule == "paper":
-            return not (dn > eps_cg * eps_cg * delta0)
-        return math.sqrt(float(np.sum(rvec * rvec))) <= tol * bnorm
-
     if bnorm == 0.0:
         return PCGResult(x, 0, True, 0.0, delta0, hist)
+
+    def rnorm(v):
+        return math.sqrt(float(np.sum(v * v)))
+
+    def stop(rvec, dn):
+        if stop_rule == "paper":
+            return not (dn > eps_cg * eps_cg * delta0)
+        return rnorm(rvec) <= tol * bnorm
+
     l = 0
-    while l < l_max:
-        if done(r, delta_new):
-            if stop_rule == "paper":
-                break
-            rt = b - apply_A(U, V, x)          # confirm on the true residual
-            if math.sqrt(float(np.sum(rt * rt))) <= tol * bnorm:
-                break
+    while l < l_max and not stop(r, delta_new):
         q = apply_A(U, V, d)
         dq = float(np.sum(d * q))
         if not (dq > 0.0):
@@ -410,6 +409,8 @@ def pcg(U, V, b, x0, M: Preconditioner, *, stop_rule: str = "relres", tol: float
             r = b - apply_A(U, V, x)
         else:
             r = r - alpha * q
+            if stop_rule == "relres" and rnorm(r) <= tol * bnorm:
+                r = b - apply_A(U, V, x)      # confirm on the true residual
         s = M.apply(r)
         delta_old = delta_new
         delta_new = float(np.sum(r * s))
@@ -417,9 +418,9 @@ def pcg(U, V, b, x0, M: Preconditioner, *, stop_rule: str = "relres", tol: float
         d = s + beta * d
         l += 1
         if record:
-            hist.append(math.sqrt(float(np.sum(r * r))) / bnorm)
+            hist.append(rnorm(r) / bnorm)
     rt = b - apply_A(U, V, x)
-    relres = math.sqrt(float(np.sum(rt * rt))) / bnorm
+    relres = rnorm(rt) / bnorm
     conv = (relres <= tol) if stop_rule == "relres" else (not delta_new > eps_cg ** 2 * delta0)
     return PCGResult(x, l, bool(conv), relres, delta0, hist)
 

@@ -1,0 +1,735 @@
+// Host driver of the batched engine: Algorithm 1 for a set of maps.
+//
+// Outer loop (all maps in lock-step, each map stops on its own):
+//   phi_prev = phi; U, V from phi (Eq. (6)); preconditioner set-up;
+//   FP64 path : b (Eq. (7)); PCG from phi^k; phi = x.
+//   mixed path: r64 = b - A phi (FP64, float weights promoted); while
+//               ||r64|| > tol ||b||: PCG (FP32, FP64 dots) on A e = r64 to a
+//               relative reduction eta; phi += e; recompute r64.
+//   outer error ||phi - phi_prev|| / ||phi_prev||.
+// The PCG loop enqueues K iterations for every running map, reads the map
+// states back once, drops finished maps from the tile lists and adapts K to
+// the predicted iterations left.
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "lpu_internal.h"
+
+namespace lpu {
+
+// engine_kernels.hip / engine_dct.hip
+void e_wrapdiff(hipStream_t st, const Engine& e, int ntiles);
+template <typename T> void e_weights(hipStream_t, const Engine&, int, double, double);
+template <typename T> void e_diag(hipStream_t, const Engine&, int, bool);
+template <typename T> void e_rhs(hipStream_t, const Engine&, int, int);
+template <typename T> void e_pass(hipStream_t, const Engine&, int, int);
+template <typename T> void e_resid(hipStream_t, const Engine&, int, int, bool);
+template <typename T> void e_spmv(hipStream_t, const Engine&, int, int);
+template <typename T> void e_update(hipStream_t, const Engine&, int, int);
+template <typename T> void e_apply(hipStream_t, const Engine&, int);
+void e_finish(hipStream_t st, const Engine& e, int op, int expect, int mode, bool pointwise,
+              bool tail_single);
+void e_dct_stage(hipStream_t st, const Engine& e, int ndtiles, int stage, int expect, int kind,
+                 const void* X, void* Out, const void* rvec);
+template <typename T> void e_pivots(hipStream_t, const Engine&, int, int, bool, double);
+template <typename T>
+void e_sweep(hipStream_t, const Engine&, int, int, int, bool, double, const void*, void*, void*);
+
+enum { kIdle = 99 };
+enum FinOpH { kFinInitH = 0, kFinAlphaH = 1, kFinUpdateH = 2, kFinConfirmH = 3, kFinTailH = 4,
+              kFinSum2H = 5 };
+enum PassOp { kPassSavePhi = 0, kPassX0Phi = 1, kPassX0Zero = 2, kPassPhiAdd = 3,
+              kPassDiffNorms = 4, kPassPhiSet = 5 };
+
+static double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+// ---------------------------------------------------------------------------
+// engine set-up
+// ---------------------------------------------------------------------------
+static void engine_free(Engine& e) {
+  void* ptrs[] = {e.desc, e.ms, e.tile_map, e.dtile_map, e.act, e.dact, e.mact, e.counts,
+                  e.dx, e.dy, e.phi_prev, e.r64, e.U, e.V, e.aux, e.x[0], e.x[1], e.d[0],
+                  e.d[1], e.r, e.s, e.q, e.b, e.t1, e.t2, e.iso, e.P};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  if (e.hms) (void)hipHostFree(e.hms);
+  if (e.hcounts) (void)hipHostFree(e.hcounts);
+  if (e.hlist) (void)hipHostFree(e.hlist);
+  e = Engine();
+}
+
+void engine_release(lp_unwrap_ctx* ctx) { engine_free(ctx->eng); }
+
+static const DctTabDev* dct_dev(lp_unwrap_ctx* ctx, int n, int* status) {
+  const DctTables* t = get_dct_tables(ctx, n, status);
+  if (!t) return nullptr;
+  for (auto& p : ctx->dct_dev)
+    if (p.first == n) return p.second;
+  DctTabDev h;
+  h.n = n;
+  h.pad = 0;
+  h.c64 = t->c64;
+  h.ct64 = t->ct64;
+  h.c32 = t->c32;
+  h.ct32 = t->ct32;
+  h.chi = t->c_hi;
+  h.clo = t->c_lo;
+  h.cthi = t->ct_hi;
+  h.ctlo = t->ct_lo;
+  h.ch = t->c_h;
+  h.cth = t->ct_h;
+  h.lam = t->lam;
+  DctTabDev* d = nullptr;
+  if (hipMalloc((void**)&d, sizeof(DctTabDev)) != hipSuccess ||
+      hipMemcpy(d, &h, sizeof(DctTabDev), hipMemcpyHostToDevice) != hipSuccess) {
+    *status = set_error(ctx, LPU_ERR_OOM, "DCT table allocation failed");
+    return nullptr;
+  }
+  ctx->dct_dev.push_back({n, d});
+  return d;
+}
+
+// Lay out n maps; (re)allocate grow-only; upload descriptors and tile maps.
+static int engine_setup(lp_unwrap_ctx* ctx, int n, const lpu_map* maps, int elem, bool need_dct) {
+  Engine& e = ctx->eng;
+  std::vector<MapDesc> hd(n);
+  long long px = 0;
+  int tiles = 0, dtiles = 0, maxN = 1;
+  for (int m = 0; m < n; ++m) {
+    MapDesc& d = hd[m];
+    std::memset(&d, 0, sizeof(d));
+    d.M = maps[m].rows;
+    d.N = maps[m].cols;
+    d.tiles_x = (d.N + kTW - 1) / kTW;
+    d.ntiles = d.tiles_x * ((d.M + kTH - 1) / kTH);
+    d.tile0 = tiles;
+    tiles += d.ntiles;
+    d.ndt = ((d.M + kDT - 1) / kDT) * ((d.N + kDT - 1) / kDT);
+    d.dtile0 = dtiles;
+    dtiles += d.ndt;
+    d.off = px;
+    px += ((long long)d.M * d.N + 63) / 64 * 64;
+    d.psi = maps[m].psi;
+    d.mask = maps[m].mask;
+    d.phi = maps[m].phi;
+    d.use_iso = maps[m].mask != nullptr ? 1 : 0;
+    maxN = std::max(maxN, d.N);
+    if (need_dct) {
+      int stt = 0;
+      d.tabM = dct_dev(ctx, d.M, &stt);
+      d.tabN = dct_dev(ctx, d.N, &stt);
+      if (!d.tabM || !d.tabN) return stt ? stt : LPU_ERR_OOM;
+    }
+  }
+  const bool grow = px > e.cap_px || tiles > e.cap_tiles || dtiles > e.cap_dtiles ||
+                    n > e.cap_maps || elem > e.elem;
+  if (grow) {
+    engine_free(e);
+    const long long cpx = std::max(px, 1LL);
+    const size_t eb = (size_t)cpx * elem;
+    const long long pst = std::max(tiles, dtiles) + 64;
+    bool ok = true;
+    auto A = [&](void** p, size_t bytes) {
+      if (ok && hipMalloc(p, std::max<size_t>(bytes, 256)) != hipSuccess) ok = false;
+    };
+    A((void**)&e.desc, sizeof(MapDesc) * n);
+    A((void**)&e.ms, sizeof(MapState) * n);
+    A((void**)&e.tile_map, 4 * (size_t)tiles);
+    A((void**)&e.dtile_map, 4 * (size_t)dtiles);
+    A((void**)&e.act, 4 * (size_t)tiles);
+    A((void**)&e.dact, 4 * (size_t)dtiles);
+    A((void**)&e.mact, 4 * (size_t)n);
+    A((void**)&e.counts, 64);
+    A((void**)&e.dx, 8 * (size_t)cpx);
+    A((void**)&e.dy, 8 * (size_t)cpx);
+    A((void**)&e.phi_prev, 8 * (size_t)cpx);
+    A((void**)&e.r64, 8 * (size_t)cpx);
+    void** tv[] = {&e.U, &e.V, &e.aux, &e.x[0], &e.x[1], &e.d[0], &e.d[1],
+                   &e.r, &e.s, &e.q, &e.b, &e.t1, &e.t2};
+    for (void** p : tv) A(p, eb);
+    A((void**)&e.iso, (size_t)cpx);
+    A((void**)&e.P, 8 * (size_t)kNumSlots * pst);
+    if (ok && hipHostMalloc((void**)&e.hms, sizeof(MapState) * n) != hipSuccess) ok = false;
+    if (ok && hipHostMalloc((void**)&e.hcounts, 64) != hipSuccess) ok = false;
+    if (ok && hipHostMalloc((void**)&e.hlist, 4 * ((size_t)tiles + dtiles + n + 16)) != hipSuccess)
+      ok = false;
+    if (!ok) {
+      engine_free(e);
+      return set_error(ctx, LPU_ERR_OOM, "engine allocation failed");
+    }
+    e.cap_px = px;
+    e.cap_tiles = tiles;
+    e.cap_dtiles = dtiles;
+    e.cap_maps = n;
+    e.elem = elem;
+    e.pstride = pst;
+    if (hipMemset(e.iso, 0, (size_t)cpx) != hipSuccess)
+      return set_error(ctx, LPU_ERR_HIP, "hipMemset");
+  }
+  e.n_maps = n;
+  e.total_px = px;
+  e.total_tiles = tiles;
+  e.total_dtiles = dtiles;
+  e.max_n = maxN;
+  e.hdesc = hd;
+  hipStream_t st = ctx->stream;
+  // descriptors and tile -> map tables (staged through the pinned list buffer)
+  std::vector<int> tm(tiles), dm(dtiles);
+  for (int m = 0; m < n; ++m) {
+    for (int t = 0; t < hd[m].ntiles; ++t) tm[hd[m].tile0 + t] = m;
+    for (int t = 0; t < hd[m].ndt; ++t) dm[hd[m].dtile0 + t] = m;
+  }
+  LPU_HIP_CHECK(ctx, hipMemcpyAsync(e.desc, hd.data(), sizeof(MapDesc) * n, hipMemcpyHostToDevice, st));
+  LPU_HIP_CHECK(ctx, hipMemcpyAsync(e.tile_map, tm.data(), 4 * (size_t)tiles, hipMemcpyHostToDevice, st));
+  LPU_HIP_CHECK(ctx, hipMemcpyAsync(e.dtile_map, dm.data(), 4 * (size_t)dtiles, hipMemcpyHostToDevice, st));
+  LPU_HIP_CHECK(ctx, hipStreamSynchronize(st));  // pageable sources
+  return LPU_OK;
+}
+
+// Make the tile lists cover exactly the maps in `set`.
+static int engine_activate(lp_unwrap_ctx* ctx, const std::vector<int>& set, int* ntiles,
+                           int* ndtiles) {
+  Engine& e = ctx->eng;
+  hipStream_t st = ctx->stream;
+  // the staging buffer may still feed a previous upload
+  if (ctx->list_event_live) {
+    LPU_HIP_CHECK(ctx, hipEventSynchronize(ctx->list_event));
+    ctx->list_event_live = false;
+  }
+  int* h = e.hlist;
+  int nt = 0;
+  for (int m : set)
+    for (int t = 0; t < e.hdesc[m].ntiles; ++t) h[nt++] = e.hdesc[m].tile0 + t;
+  int* hd = h + nt;
+  int nd = 0;
+  for (int m : set)
+    for (int t = 0; t < e.hdesc[m].ndt; ++t) hd[nd++] = e.hdesc[m].dtile0 + t;
+  int* hm = hd + nd;
+  int nm = 0;
+  for (int m : set) hm[nm++] = m;
+  int* hc = hm + nm;
+  hc[0] = nt;
+  hc[1] = nd;
+  hc[2] = nm;
+  if (nt) LPU_HIP_CHECK(ctx, hipMemcpyAsync(e.act, h, 4 * (size_t)nt, hipMemcpyHostToDevice, st));
+  if (nd) LPU_HIP_CHECK(ctx, hipMemcpyAsync(e.dact, hd, 4 * (size_t)nd, hipMemcpyHostToDevice, st));
+  if (nm) LPU_HIP_CHECK(ctx, hipMemcpyAsync(e.mact, hm, 4 * (size_t)nm, hipMemcpyHostToDevice, st));
+  LPU_HIP_CHECK(ctx, hipMemcpyAsync(e.counts, hc, 12, hipMemcpyHostToDevice, st));
+  LPU_HIP_CHECK(ctx, hipEventRecord(ctx->list_event, st));
+  ctx->list_event_live = true;
+  *ntiles = nt;
+  *ndtiles = nd;
+  return LPU_OK;
+}
+
+static int read_states(lp_unwrap_ctx* ctx) {
+  Engine& e = ctx->eng;
+  LPU_HIP_CHECK(ctx, hipMemcpyAsync(e.hms, e.ms, sizeof(MapState) * e.n_maps,
+                                    hipMemcpyDeviceToHost, ctx->stream));
+  LPU_HIP_CHECK(ctx, hipStreamSynchronize(ctx->stream));
+  return LPU_OK;
+}
+
+static int write_states(lp_unwrap_ctx* ctx) {
+  Engine& e = ctx->eng;
+  LPU_HIP_CHECK(ctx, hipMemcpyAsync(e.ms, e.hms, sizeof(MapState) * e.n_maps,
+                                    hipMemcpyHostToDevice, ctx->stream));
+  LPU_HIP_CHECK(ctx, hipStreamSynchronize(ctx->stream));
+  return LPU_OK;
+}
+
+// ---------------------------------------------------------------------------
+// PCG over a set of maps
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Pcg {
+  lp_unwrap_ctx* ctx;
+  int pc, dct_kind;
+  double omega;
+
+  bool pointwise() const { return pc == kPcNone || pc == kPcJacobi; }
+
+  void tail(int ndt, int nmaps, int expect) {
+    Engine& e = ctx->eng;
+    hipStream_t st = ctx->stream;
+    KTimer& kt = ctx->kt;
+    if (pc == kPcDct) {
+      const void* in[4] = {e.r, e.t1, e.t2, e.t1};
+      void* out[4] = {e.t1, e.t2, e.t1, e.s};
+      for (int s = 0; s < 4; ++s) {
+        const int ev = kt.begin(LPU_KC_DCT, st);
+        e_dct_stage(st, e, ndt, s, expect, dct_kind, in[s], out[s], e.r);
+        kt.end(ev, LPU_KC_DCT, st);
+      }
+    } else {
+      const int ev = kt.begin(LPU_KC_SWEEP, st);
+      e_sweep<T>(st, e, nmaps, e.max_n, expect, pc == kPcSsor, omega, e.r, e.s, e.t1);
+      kt.end(ev, LPU_KC_SWEEP, st);
+    }
+  }
+
+  void fin(int op, int expect, int mode = kFinishNone) {
+    const bool single = !(pc == kPcDct);
+    e_finish(ctx->stream, ctx->eng, op, expect, mode, pointwise(), single);
+  }
+
+  // Run PCG for the maps in `set` from x0; per-map tol2 already in hms.
+  // Returns LPU_OK or an error; per-map final states/iterations are in hms.
+  int run(std::vector<int> set, int rule, double eps, const std::vector<double>& tol,
+          const std::vector<long long>& lmax, const std::vector<long long>& period) {
+    Engine& e = ctx->eng;
+    hipStream_t st = ctx->stream;
+    KTimer& kt = ctx->kt;
+    int rc;
+    for (int m = 0; m < e.n_maps; ++m) e.hms[m].state = kIdle;
+    for (size_t k = 0; k < set.size(); ++k) {
+      MapState& s = e.hms[set[k]];
+      std::memset(&s, 0, sizeof(s));
+      s.tol2 = tol[k] * tol[k];
+      s.eps2 = eps * eps;
+      s.l_max = lmax[k];
+      s.period = period[k];
+      s.rule = rule;
+      s.state = kRun;
+    }
+    if ((rc = write_states(ctx))) return rc;
+    int nt = 0, nd = 0;
+    if ((rc = engine_activate(ctx, set, &nt, &nd))) return rc;
+    const bool pw = pointwise();
+    int ev = kt.begin(LPU_KC_INIT, st);
+    e_resid<T>(st, e, nt, pc, false);
+    kt.end(ev, LPU_KC_INIT, st);
+    fin(kFinInitH, kRun);
+    if (!pw) {
+      tail(nd, (int)set.size(), kInitPc);
+      fin(kFinTailH, kInitPc, kFinishInit);
+    }
+    long long K = 4;
+    std::vector<double> prev_metric(e.n_maps, -1.0);
+    std::vector<long long> prev_l(e.n_maps, 0);
+    for (;;) {
+      for (long long k = 0; k < K; ++k) {
+        ev = kt.begin(LPU_KC_SPMV, st);
+        e_spmv<T>(st, e, nt, pc);
+        kt.end(ev, LPU_KC_SPMV, st);
+        fin(kFinAlphaH, kRun);
+        ev = kt.begin(LPU_KC_UPDATE, st);
+        e_update<T>(st, e, nt, pc);
+        kt.end(ev, LPU_KC_UPDATE, st);
+        fin(kFinUpdateH, kRun);
+        if (!pw) {
+          tail(nd, (int)set.size(), kRun);
+          fin(kFinTailH, kRun, kFinishIter);
+        }
+      }
+      ev = kt.begin(LPU_KC_CONFIRM, st);
+      e_resid<T>(st, e, nt, pc, true);
+      kt.end(ev, LPU_KC_CONFIRM, st);
+      fin(kFinConfirmH, kConfirm);
+      if (!pw) {
+        tail(nd, (int)set.size(), kConfirmPc);
+        fin(kFinTailH, kConfirmPc, kFinishConfirm);
+      }
+      if ((rc = read_states(ctx))) return rc;
+      std::vector<int> still;
+      long long nextK = 64;
+      for (int m : set) {
+        const MapState& s = e.hms[m];
+        if (s.state == kDone || s.state == kCap || s.state == kBreakdown) continue;
+        still.push_back(m);
+        const double metric = rule == LPU_STOP_PAPER ? s.delta_new : s.rr;
+        const double target = rule == LPU_STOP_PAPER ? s.thr_delta : s.thr_rr;
+        long long guess = 2 * K;
+        if (prev_metric[m] > 0.0 && metric > 0.0 && s.l > prev_l[m] && metric < prev_metric[m]) {
+          const double rate = std::log(metric / prev_metric[m]) / (double)(s.l - prev_l[m]);
+          const double left = std::log(target / metric) / rate;
+          if (std::isfinite(left)) guess = (long long)std::ceil(left * 0.9) + 1;
+        }
+        prev_metric[m] = metric;
+        prev_l[m] = s.l;
+        nextK = std::min(nextK, guess);
+      }
+      if (still.empty()) break;
+      if (still.size() != set.size()) {
+        set = still;
+        if ((rc = engine_activate(ctx, set, &nt, &nd))) return rc;
+      }
+      K = std::max(2LL, std::min(nextK, 64LL));
+    }
+    return LPU_OK;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Algorithm 1 for a set of maps
+// ---------------------------------------------------------------------------
+template <typename T>
+static int run_maps(lp_unwrap_ctx* ctx, int n, const lpu_map* maps, double p, double tau, int pc,
+                    double tol, const lpu_options& o, lpu_stats* stats) {
+  const double t_start = now_ms();
+  hipStream_t st = ctx->stream;
+  const bool mixed = sizeof(T) == 4;
+  int rc = engine_setup(ctx, n, maps, (int)sizeof(T), pc == kPcDct);
+  if (rc) return rc;
+  Engine& e = ctx->eng;
+  KTimer& kt = ctx->kt;
+
+  // inputs must be finite (mask in [0, 1])
+  LPU_HIP_CHECK(ctx, hipMemsetAsync(e.counts + 8, 0, 4, st));
+  for (int m = 0; m < n; ++m)
+    launch_finite_check(st, (size_t)maps[m].rows * maps[m].cols, maps[m].psi, maps[m].mask,
+                        (unsigned int*)(e.counts + 8));
+  unsigned int bad = 0;
+  LPU_HIP_CHECK(ctx, hipMemcpyAsync(&bad, e.counts + 8, 4, hipMemcpyDeviceToHost, st));
+  LPU_HIP_CHECK(ctx, hipStreamSynchronize(st));
+  if (bad) return set_error(ctx, LPU_ERR_NONFINITE, "psi or mask holds NaN/Inf (or mask outside [0,1])");
+
+  for (int m = 0; m < n; ++m)
+    if (!o.use_phi0)
+      LPU_HIP_CHECK(ctx, hipMemsetAsync(maps[m].phi, 0, sizeof(double) * maps[m].rows * maps[m].cols, st));
+
+  std::vector<int> all(n);
+  for (int m = 0; m < n; ++m) all[m] = m;
+  int nt = 0, nd = 0;
+  if ((rc = engine_activate(ctx, all, &nt, &nd))) return rc;
+  e_wrapdiff(st, e, nt);
+
+  const bool need_diag = pc == kPcJacobi;
+  bool any_mask = false;
+  for (int m = 0; m < n; ++m) any_mask |= maps[m].mask != nullptr;
+
+  std::vector<long long> lmax(n), period(n);
+  for (int m = 0; m < n; ++m) {
+    const long long px = (long long)maps[m].rows * maps[m].cols;
+    lmax[m] = o.l_max > 0 ? o.l_max : 2 * px;
+    period[m] = o.residual_period > 0 ? o.residual_period
+                                      : std::max(1LL, (long long)std::floor(std::sqrt((double)px)));
+  }
+  std::vector<int> outer(n, 0), refinements(n, 0), status(n, LPU_OK);
+  std::vector<long long> inner(n, 0);
+  std::vector<double> err(n, INFINITY), relres(n, 0.0);
+  std::vector<bool> finished(n, false), outer_conv(n, false), inner_ok(n, true);
+  double setup_ms = 0.0;
+  Pcg<T> pcg{ctx, pc, mixed ? (o.dct_mode == LPU_DCT_FP32 ? 1 : (o.dct_mode == LPU_DCT_SPLIT_BF16 ? 2 : 3)) : 0,
+             o.ssor_omega};
+
+  auto credit = [&](const std::vector<int>& set) {
+    // algorithmic figures of the PCG launches that did work
+    for (int m : set) {
+      const MapState& s = e.hms[m];
+      const double px = (double)maps[m].rows * maps[m].cols, el = (double)sizeof(T);
+      const double jac = pc == kPcJacobi ? 1.0 : 0.0;
+      kt.credit(LPU_KC_SPMV, s.l, s.l * px * el * (6.0 + jac), s.l * px * 13.0);
+      kt.credit(LPU_KC_UPDATE, s.l, s.l * px * el * (6.0 + jac), s.l * px * 8.0);
+      const double Mm = maps[m].rows, Nn = maps[m].cols;
+      if (pc == kPcDct) {
+        const double prod = pcg.dct_kind == 2 ? 3.0 : 1.0;
+        const double tab = pcg.dct_kind == 0 ? 8.0 : (pcg.dct_kind == 1 ? 4.0 : (pcg.dct_kind == 2 ? 4.0 : 2.0));
+        const double bytes = 2.0 * (2.0 * px * el + Nn * Nn * tab) + 2.0 * (2.0 * px * el + Mm * Mm * tab) + px * el;
+        kt.credit(LPU_KC_DCT, 4 * s.nfinish, s.nfinish * bytes, s.nfinish * 4.0 * px * (Mm + Nn) * prod);
+      } else if (!pcg.pointwise()) {
+        kt.credit(LPU_KC_SWEEP, s.nfinish, s.nfinish * px * el * 10.0, s.nfinish * px * 14.0);
+      }
+    }
+  };
+
+  for (int k = 0; k < o.k_max; ++k) {
+    std::vector<int> act;
+    for (int m = 0; m < n; ++m)
+      if (!finished[m]) act.push_back(m);
+    if (act.empty()) break;
+    const double ts = now_ms();
+    if ((rc = engine_activate(ctx, act, &nt, &nd))) return rc;
+    const int ev = kt.begin(LPU_KC_SETUP, st);
+    e_pass<T>(st, e, nt, kPassSavePhi);
+    e_weights<T>(st, e, nt, p, tau);
+    if (need_diag || any_mask) e_diag<T>(st, e, nt, need_diag);
+    if (pc == kPcIlu || pc == kPcIc || pc == kPcSsor)
+      e_pivots<T>(st, e, (int)act.size(), e.max_n, pc == kPcSsor, o.ssor_omega);
+    kt.end(ev, LPU_KC_SETUP, st);
+    if (!mixed) {
+      e_rhs<T>(st, e, nt, 0);
+      e_pass<T>(st, e, nt, kPassX0Phi);
+      setup_ms += now_ms() - ts;
+      std::vector<double> tl(act.size(), tol);
+      std::vector<long long> lm, pr;
+      for (int m : act) lm.push_back(lmax[m]), pr.push_back(period[m]);
+      if ((rc = pcg.run(act, o.stop_rule, o.eps_cg, tl, lm, pr))) return rc;
+      credit(act);
+      for (int m : act) {
+        const MapState& s = e.hms[m];
+        inner[m] += s.l;
+        refinements[m] += 1;
+        inner_ok[m] = s.state == kDone;
+        if (s.state == kBreakdown) status[m] = LPU_ERR_BREAKDOWN, finished[m] = true;
+      }
+      if ((rc = engine_activate(ctx, act, &nt, &nd))) return rc;
+      e_pass<T>(st, e, nt, kPassPhiSet);
+    } else {
+      e_rhs<T>(st, e, nt, 1);
+      e_finish(st, e, kFinSum2H, -1, kFinishNone, true, true);
+      if ((rc = read_states(ctx))) return rc;
+      setup_ms += now_ms() - ts;
+      std::vector<double> rr(n, 0.0), bb(n, 0.0);
+      for (int m : act) rr[m] = e.hms[m].rr, bb[m] = e.hms[m].bb;
+      std::vector<int> ref;
+      for (int m : act)
+        if (bb[m] > 0.0 && rr[m] > tol * tol * bb[m]) ref.push_back(m);
+      for (int j = 0; !ref.empty() && j < o.max_refine; ++j) {
+        std::vector<double> tl;
+        std::vector<long long> lm, pr;
+        for (int m : ref) {
+          double eta = o.refine_eta;
+          if (o.stop_rule == LPU_STOP_RELRES) eta = std::max(eta, 0.5 * tol / std::sqrt(rr[m] / bb[m]));
+          tl.push_back(std::min(eta, 0.5));
+          lm.push_back(lmax[m]);
+          pr.push_back(period[m]);
+        }
+        if ((rc = engine_activate(ctx, ref, &nt, &nd))) return rc;
+        e_pass<T>(st, e, nt, kPassX0Zero);
+        if ((rc = pcg.run(ref, o.stop_rule, o.eps_cg, tl, lm, pr))) return rc;
+        credit(ref);
+        std::vector<int> cont, okm;
+        for (int m : ref) {
+          const MapState& s = e.hms[m];
+          inner[m] += s.l;
+          refinements[m] += 1;
+          if (s.state == kBreakdown) status[m] = LPU_ERR_BREAKDOWN, finished[m] = true;
+          else okm.push_back(m);
+        }
+        if (okm.empty()) break;
+        ref = okm;
+        if ((rc = engine_activate(ctx, ref, &nt, &nd))) return rc;
+        e_pass<T>(st, e, nt, kPassPhiAdd);
+        e_rhs<T>(st, e, nt, 1);
+        e_finish(st, e, kFinSum2H, -1, kFinishNone, true, true);
+        if ((rc = read_states(ctx))) return rc;
+        for (int m : ref) {
+          if (finished[m]) continue;
+          rr[m] = e.hms[m].rr;
+          if (o.stop_rule != LPU_STOP_PAPER && rr[m] > tol * tol * bb[m]) cont.push_back(m);
+        }
+        ref = cont;
+      }
+      for (int m : act)
+        inner_ok[m] = o.stop_rule == LPU_STOP_PAPER || bb[m] == 0.0 || rr[m] <= tol * tol * bb[m];
+    }
+    // outer error
+    std::vector<int> act2;
+    for (int m : act)
+      if (!finished[m]) act2.push_back(m);
+    if (act2.empty()) break;
+    if ((rc = engine_activate(ctx, act2, &nt, &nd))) return rc;
+    e_pass<T>(st, e, nt, kPassDiffNorms);
+    e_finish(st, e, kFinSum2H, -1, kFinishNone, true, true);
+    if ((rc = read_states(ctx))) return rc;
+    for (int m : act2) {
+      outer[m] = k + 1;
+      const double dn = e.hms[m].rr, pn = e.hms[m].bb;
+      err[m] = pn > 0.0 ? std::sqrt(dn / pn) : INFINITY;
+      if (o.outer_tol > 0.0 && err[m] <= o.outer_tol) outer_conv[m] = true, finished[m] = true;
+    }
+  }
+  // FP64 relative residual of each map's last system
+  std::vector<int> done_any;
+  for (int m = 0; m < n; ++m)
+    if (outer[m] > 0 && status[m] >= 0) done_any.push_back(m);
+  if (!done_any.empty()) {
+    if ((rc = engine_activate(ctx, done_any, &nt, &nd))) return rc;
+    e_rhs<T>(st, e, nt, 2);
+    e_finish(st, e, kFinSum2H, -1, kFinishNone, true, true);
+    if ((rc = read_states(ctx))) return rc;
+    for (int m : done_any)
+      relres[m] = e.hms[m].bb > 0 ? std::sqrt(e.hms[m].rr / e.hms[m].bb) : 0.0;
+  }
+  int worst = LPU_OK;
+  const double total_ms = now_ms() - t_start;
+  for (int m = 0; m < n; ++m) {
+    if (status[m] >= 0) {
+      if (o.outer_tol > 0.0) status[m] = outer_conv[m] ? LPU_OK : LPU_NOT_CONVERGED;
+      else status[m] = inner_ok[m] ? LPU_OK : LPU_NOT_CONVERGED;
+      if (o.k_max == 0) status[m] = LPU_OK;
+    }
+    if (status[m] < 0 && (worst >= 0 || status[m] < worst)) worst = status[m];
+    else if (worst >= 0 && status[m] > worst) worst = status[m];
+    if (stats) {
+      lpu_stats& s = stats[m];
+      s.outer_iters = outer[m];
+      s.inner_iters_total = inner[m];
+      s.refinements = refinements[m];
+      s.final_relres = relres[m];
+      s.outer_err = err[m];
+      s.setup_ms = setup_ms;
+      s.solve_ms = total_ms;
+      s.converged = status[m] == LPU_OK;
+      s.status = status[m];
+    }
+  }
+  if (worst == LPU_ERR_BREAKDOWN) set_error(ctx, worst, "PCG breakdown");
+  return worst;
+}
+
+int engine_solve(lp_unwrap_ctx* ctx, int n, const lpu_map* maps, double p, double tau, int pc,
+                 double tol, const lpu_options& o, lpu_stats* stats) {
+  if (o.precision == LPU_FP64) return run_maps<double>(ctx, n, maps, p, tau, pc, tol, o, stats);
+  return run_maps<float>(ctx, n, maps, p, tau, pc, tol, o, stats);
+}
+
+// ---------------------------------------------------------------------------
+// Step entry points: one map through the engine's kernels
+// ---------------------------------------------------------------------------
+static int step_setup(lp_unwrap_ctx* ctx, int M, int N, int elem, bool dct, const double* psi,
+                      const float* mask, double* phi) {
+  lpu_map mp;
+  mp.rows = M;
+  mp.cols = N;
+  mp.psi = psi;
+  mp.mask = mask;
+  mp.phi = phi;
+  int rc = engine_setup(ctx, 1, &mp, elem, dct);
+  if (rc) return rc;
+  std::vector<int> one(1, 0);
+  int nt, nd;
+  return engine_activate(ctx, one, &nt, &nd);
+}
+
+static int copy_in(lp_unwrap_ctx* ctx, void* dst, const void* src, size_t bytes) {
+  LPU_HIP_CHECK(ctx, hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, ctx->stream));
+  return LPU_OK;
+}
+
+int step_wrapdiff(lp_unwrap_ctx* ctx, int M, int N, const double* psi, double* dx, double* dy) {
+  int rc = step_setup(ctx, M, N, 8, false, psi, nullptr, nullptr);
+  if (rc) return rc;
+  Engine& e = ctx->eng;
+  e_wrapdiff(ctx->stream, e, e.total_tiles);
+  const size_t b = (size_t)M * N * 8;
+  if ((rc = copy_in(ctx, dx, e.dx, b)) || (rc = copy_in(ctx, dy, e.dy, b))) return rc;
+  LPU_HIP_CHECK(ctx, hipStreamSynchronize(ctx->stream));
+  return LPU_OK;
+}
+
+template <typename T>
+int step_weights(lp_unwrap_ctx* ctx, int M, int N, const double* phi, const double* dx,
+                 const double* dy, const float* mask, double p, double tau, T* U, T* V) {
+  int rc = step_setup(ctx, M, N, sizeof(T), false, nullptr, mask, const_cast<double*>(phi));
+  if (rc) return rc;
+  Engine& e = ctx->eng;
+  const size_t n = (size_t)M * N;
+  if ((rc = copy_in(ctx, e.dx, dx, n * 8)) || (rc = copy_in(ctx, e.dy, dy, n * 8))) return rc;
+  e_weights<T>(ctx->stream, e, e.total_tiles, p, tau);
+  if ((rc = copy_in(ctx, U, e.U, n * sizeof(T))) || (rc = copy_in(ctx, V, e.V, n * sizeof(T))))
+    return rc;
+  LPU_HIP_CHECK(ctx, hipStreamSynchronize(ctx->stream));
+  return LPU_OK;
+}
+
+template <typename T>
+int step_apply(lp_unwrap_ctx* ctx, int M, int N, const T* U, const T* V, const T* x, T* y) {
+  int rc = step_setup(ctx, M, N, sizeof(T), false, nullptr, nullptr, nullptr);
+  if (rc) return rc;
+  Engine& e = ctx->eng;
+  const size_t b = (size_t)M * N * sizeof(T);
+  if ((rc = copy_in(ctx, e.U, U, b)) || (rc = copy_in(ctx, e.V, V, b)) || (rc = copy_in(ctx, e.s, x, b)))
+    return rc;
+  e_apply<T>(ctx->stream, e, e.total_tiles);
+  if ((rc = copy_in(ctx, y, e.q, b))) return rc;
+  LPU_HIP_CHECK(ctx, hipStreamSynchronize(ctx->stream));
+  return LPU_OK;
+}
+
+template <typename T>
+int step_rhs(lp_unwrap_ctx* ctx, int M, int N, const T* U, const T* V, const double* dx,
+             const double* dy, double* b) {
+  int rc = step_setup(ctx, M, N, sizeof(T), false, nullptr, nullptr, nullptr);
+  if (rc) return rc;
+  Engine& e = ctx->eng;
+  const size_t n = (size_t)M * N;
+  if ((rc = copy_in(ctx, e.U, U, n * sizeof(T))) || (rc = copy_in(ctx, e.V, V, n * sizeof(T))) ||
+      (rc = copy_in(ctx, e.dx, dx, n * 8)) || (rc = copy_in(ctx, e.dy, dy, n * 8)))
+    return rc;
+  e_rhs<T>(ctx->stream, e, e.total_tiles, 0);
+  if ((rc = copy_in(ctx, b, e.r64, n * 8))) return rc;
+  LPU_HIP_CHECK(ctx, hipStreamSynchronize(ctx->stream));
+  return LPU_OK;
+}
+
+template <typename T>
+int step_pivots(lp_unwrap_ctx* ctx, int M, int N, const T* U, const T* V, T* piv, bool ssor,
+                double omega) {
+  int rc = step_setup(ctx, M, N, sizeof(T), false, nullptr, nullptr, nullptr);
+  if (rc) return rc;
+  Engine& e = ctx->eng;
+  const size_t b = (size_t)M * N * sizeof(T);
+  if ((rc = copy_in(ctx, e.U, U, b)) || (rc = copy_in(ctx, e.V, V, b))) return rc;
+  e_pivots<T>(ctx->stream, e, 1, N, ssor, omega);
+  if ((rc = copy_in(ctx, piv, e.aux, b))) return rc;
+  LPU_HIP_CHECK(ctx, hipStreamSynchronize(ctx->stream));
+  return LPU_OK;
+}
+
+template <typename T>
+int step_precond(lp_unwrap_ctx* ctx, int M, int N, int pc, int dct_mode, double omega, const T* U,
+                 const T* V, const T* r, T* s) {
+  int rc = step_setup(ctx, M, N, sizeof(T), pc == kPcDct, nullptr, nullptr, nullptr);
+  if (rc) return rc;
+  Engine& e = ctx->eng;
+  hipStream_t st = ctx->stream;
+  const size_t n = (size_t)M * N, b = n * sizeof(T);
+  if ((rc = copy_in(ctx, e.U, U, b)) || (rc = copy_in(ctx, e.V, V, b)) || (rc = copy_in(ctx, e.r, r, b)))
+    return rc;
+  // preconditioner output is zeroed on isolated pixels
+  e.hdesc[0].use_iso = 1;
+  LPU_HIP_CHECK(ctx, hipMemcpyAsync(e.desc, e.hdesc.data(), sizeof(MapDesc), hipMemcpyHostToDevice, st));
+  LPU_HIP_CHECK(ctx, hipStreamSynchronize(st));
+  e_diag<T>(st, e, e.total_tiles, pc == kPcJacobi);
+  MapState& h = e.hms[0];
+  std::memset(&h, 0, sizeof(h));
+  h.state = kRun;
+  if (pc == kPcDct && sizeof(T) == 4 && dct_mode == LPU_DCT_FP16_SCALED) {
+    // the scaled-fp16 stage 0 needs ||r||^2
+    std::vector<T> hr(n);
+    LPU_HIP_CHECK(ctx, hipMemcpy(hr.data(), r, b, hipMemcpyDeviceToHost));
+    double rr = 0.0;
+    for (T v : hr) rr += (double)v * (double)v;
+    h.rr = rr;
+  }
+  if ((rc = write_states(ctx))) return rc;
+  if (pc == kPcNone) {
+    if ((rc = copy_in(ctx, s, r, b))) return rc;
+  } else if (pc == kPcJacobi) {
+    launch_scale_by<T>(st, n, r, (const T*)e.aux, s);
+  } else if (pc == kPcDct) {
+    const int kind = sizeof(T) == 8 ? 0 : (dct_mode == LPU_DCT_FP32 ? 1 : (dct_mode == LPU_DCT_SPLIT_BF16 ? 2 : 3));
+    const void* in[4] = {e.r, e.t1, e.t2, e.t1};
+    void* out[4] = {e.t1, e.t2, e.t1, e.s};
+    for (int k = 0; k < 4; ++k) e_dct_stage(st, e, e.total_dtiles, k, kRun, kind, in[k], out[k], e.r);
+    if ((rc = copy_in(ctx, s, e.s, b))) return rc;
+  } else {
+    e_pivots<T>(st, e, 1, N, pc == kPcSsor, omega);
+    e_sweep<T>(st, e, 1, N, kRun, pc == kPcSsor, omega, e.r, e.s, e.t1);
+    if ((rc = copy_in(ctx, s, e.s, b))) return rc;
+  }
+  LPU_HIP_CHECK(ctx, hipStreamSynchronize(st));
+  return LPU_OK;
+}
+
+#define LPU_INST_STEP(T)                                                                          \
+  template int step_weights<T>(lp_unwrap_ctx*, int, int, const double*, const double*,            \
+                               const double*, const float*, double, double, T*, T*);               \
+  template int step_apply<T>(lp_unwrap_ctx*, int, int, const T*, const T*, const T*, T*);          \
+  template int step_rhs<T>(lp_unwrap_ctx*, int, int, const T*, const T*, const double*,            \
+                           const double*, double*);                                                \
+  template int step_pivots<T>(lp_unwrap_ctx*, int, int, const T*, const T*, T*, bool, double);     \
+  template int step_precond<T>(lp_unwrap_ctx*, int, int, int, int, double, const T*, const T*,     \
+                               const T*, T*);
+LPU_INST_STEP(float)
+LPU_INST_STEP(double)
+
+}  // namespace lpu

@@ -1,0 +1,109 @@
+// Batched PCG engine: data layout shared by the kernels and the host driver.
+//
+// Every solve -- one map or many -- runs on an Engine: the maps' work vectors
+// are concatenated (each map contiguous, row-major, at a 64-element aligned
+// offset), and every kernel walks a device-resident list of active tiles
+// (grid-stride, fixed grid), so one launch serves all maps of a phase and maps
+// that have stopped cost nothing once the host compacts the list.
+//
+// Reductions: each tile writes its FP64 partial sums to its own slot; a
+// finisher kernel (one block per map) sums the map's slots in a fixed order
+// and advances that map's PCG state.  No atomics and no grid-wide fences, so
+// results are deterministic and nothing serialises across the chip's L2s.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+namespace lpu {
+
+constexpr int kTW = 128;  // stencil tile width (columns): two per lane of one wave
+constexpr int kTH = 16;   // stencil tile height (rows), marched by the wave
+constexpr int kDT = 64;   // DCT output tile (64 x 64)
+constexpr int kEngineGrid = 4096;  // blocks of the grid-stride tile kernels
+constexpr int kNumSlots = 4;       // partial-sum slots
+
+// DCT tables of one size n as seen by the kernels.
+struct DctTabDev {
+  int n;
+  int pad;
+  const double* c64;
+  const double* ct64;
+  const float* c32;
+  const float* ct32;
+  const uint16_t* chi;
+  const uint16_t* clo;
+  const uint16_t* cthi;
+  const uint16_t* ctlo;
+  const uint16_t* ch;
+  const uint16_t* cth;
+  const double* lam;
+};
+
+struct MapDesc {
+  int M, N;
+  int tiles_x, ntiles, tile0;  // stencil tiles
+  int ndt, dtile0;             // DCT tiles (same count in every stage)
+  int use_iso;                 // zero the preconditioner output on isolated pixels
+  long long off;               // element offset of this map in the work vectors
+  const double* psi;           // caller's wrapped phase
+  const float* mask;           // caller's quality mask or null
+  double* phi;                 // caller's solution (FP64)
+  const DctTabDev* tabM;
+  const DctTabDev* tabN;
+};
+
+// PCG state of one map (written only by finisher kernels and by the host).
+struct MapState {
+  double delta_new, delta_old, delta0;
+  double alpha, beta;
+  double dq, rr, bb, rs;
+  double thr_rr, thr_delta, tol2, eps2;
+  long long l, l_max, period, nfinish;
+  int state, rule, replaced, pad;
+  float amax[4];
+};
+
+struct Engine {
+  int elem = 0;              // sizeof(T) of the vectors this engine was sized for
+  int n_maps = 0, cap_maps = 0;
+  long long total_px = 0, cap_px = 0;
+  int total_tiles = 0, total_dtiles = 0, cap_tiles = 0, cap_dtiles = 0;
+  int max_n = 1;             // widest map (sweep kernels)
+  std::vector<MapDesc> hdesc;
+  MapDesc* desc = nullptr;
+  MapState* ms = nullptr;
+  MapState* hms = nullptr;   // pinned mirror
+  int* tile_map = nullptr;   // global stencil tile -> map
+  int* dtile_map = nullptr;  // global DCT tile -> map
+  int* act = nullptr;        // active stencil tiles
+  int* dact = nullptr;       // active DCT tiles
+  int* mact = nullptr;       // active maps (sweep kernels)
+  int* counts = nullptr;     // [0] active tiles, [1] active DCT tiles, [2] active maps
+  int* hcounts = nullptr;    // pinned
+  int* hlist = nullptr;      // pinned staging for the lists
+  // FP64 arrays
+  double* dx = nullptr;
+  double* dy = nullptr;
+  double* phi_prev = nullptr;
+  double* r64 = nullptr;
+  // T arrays (elem bytes per pixel)
+  void* U = nullptr;
+  void* V = nullptr;
+  void* aux = nullptr;
+  void* x[2] = {nullptr, nullptr};
+  void* d[2] = {nullptr, nullptr};
+  void* r = nullptr;
+  void* s = nullptr;
+  void* q = nullptr;
+  void* b = nullptr;
+  void* t1 = nullptr;
+  void* t2 = nullptr;
+  unsigned char* iso = nullptr;  // isolated-pixel flags
+  double* P = nullptr;           // partials: kNumSlots x pstride
+  long long pstride = 0;
+};
+
+}  // namespace lpu

@@ -1,0 +1,589 @@
+// Batched preconditioner kernels: the DCT Poisson solve (grouped contractions
+// over all active maps) and the natural-order sweeps (one workgroup per map).
+//
+// DCT (s = L0^+ r, L0 the unit-weight Neumann Laplacian):
+//   s = C_M^T [ (C_M r C_N^T) ./ Lambda ] C_N,
+//   C_n[k][j] = s_k cos(pi k (2j+1) / (2n)), Lambda_kl = (2 - 2cos(pi k/M)) + (2 - 2cos(pi l/N)),
+//   zero mode dropped.  Four stages of Out^T = X B^T (rows of X transformed by
+//   the basis in B, result stored transposed):
+//     stage 0: X = r  (M x N), B = C_N   -> t1 (N x M)
+//     stage 1: X = t1 (N x M), B = C_M   -> t2 (M x N), t2 ./= Lambda
+//     stage 2: X = t2 (M x N), B = C_N^T -> t1 (N x M)
+//     stage 3: X = t1 (N x M), B = C_M^T -> s  (M x N), zero on isolated pixels,
+//              FP64 partial of r^T s per 64 x 64 tile.
+// Every map contributes ceil(M/64) ceil(N/64) output tiles to every stage.
+
+#include "lpu_internal.h"
+#include "lpu_device.h"
+
+namespace lpu {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+
+struct DArgs {
+  const MapDesc* desc;
+  MapState* ms;
+  const int* dtile_map;
+  const int* dact;
+  const int* counts;
+  double* P;
+  long long pstride;
+  const void* X;
+  void* Out;
+  const void* rvec;
+  const unsigned char* iso;
+  int stage, expect;
+};
+
+struct DTile {
+  int m, R, K, r0, c0;
+  long long off;
+  const DctTabDev* tab;
+  bool ok;
+};
+
+__device__ __forceinline__ DTile dtile(const DArgs& a, int g) {
+  DTile t;
+  t.m = a.dtile_map[g];
+  const MapDesc& d = a.desc[t.m];
+  t.ok = a.ms[t.m].state == a.expect;
+  const bool rows_m = (a.stage & 1) == 0;
+  t.R = rows_m ? d.M : d.N;
+  t.K = rows_m ? d.N : d.M;
+  const int tiles_r = (t.R + kDT - 1) / kDT;
+  const int local = g - d.dtile0;
+  t.r0 = (local % tiles_r) * kDT;
+  t.c0 = (local / tiles_r) * kDT;
+  t.off = d.off;
+  t.tab = rows_m ? d.tabN : d.tabM;
+  return t;
+}
+
+// ---------------------------------------------------------------------------
+// MFMA stage (mixed path): 4 waves, 32 x 32 outputs each, K step 32; lane l
+// supplies row (l mod 16) and K values 8*(l/16) .. +7 of the 16x16x32 ops.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ f32x8 load_x8(const float* __restrict__ X, int R, int K, int row, int k,
+                                         bool vec_ok) {
+  f32x8 v;
+  if (row < R && vec_ok && k + 7 < K) {
+    const float4* p = reinterpret_cast<const float4*>(X + (size_t)row * K + k);
+    const float4 a = p[0], b = p[1];
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+  } else {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = (row < R && k + e < K) ? X[(size_t)row * K + k + e] : 0.0f;
+  }
+  return v;
+}
+
+__device__ __forceinline__ u16x8 load_t8(const uint16_t* __restrict__ B, int K, int row, int k,
+                                         bool vec_ok) {
+  u16x8 v;
+  if (row < K && vec_ok && k + 7 < K) {
+    v = *reinterpret_cast<const u16x8*>(B + (size_t)row * K + k);
+  } else {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = (row < K && k + e < K) ? B[(size_t)row * K + k + e] : 0;
+  }
+  return v;
+}
+
+__device__ __forceinline__ float fp16_scale(float amax) {
+  if (!(amax > 0.0f) || !isfinite(amax)) return 1.0f;
+  int e;
+  frexpf(amax, &e);
+  return ldexpf(1.0f, 14 - e);
+}
+
+template <int SPLIT>
+__global__ void __launch_bounds__(256) k_e_dct_mfma(DArgs a) {
+  __shared__ double red[4];
+  const int nact = a.counts[1];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int t_ = blockIdx.x; t_ < nact; t_ += gridDim.x) {
+    const int g = a.dact[t_];
+    const DTile t = dtile(a, g);
+    if (!t.ok) continue;  // uniform over the block
+    const int R = t.R, K = t.K;
+    const float* X = reinterpret_cast<const float*>(a.X) + t.off;
+    float* Out = reinterpret_cast<float*>(a.Out) + t.off;
+    const uint16_t* Bh;
+    const uint16_t* Bl;
+    if (a.stage < 2) {
+      Bh = SPLIT ? t.tab->chi : t.tab->ch;
+      Bl = t.tab->clo;
+    } else {
+      Bh = SPLIT ? t.tab->cthi : t.tab->cth;
+      Bl = t.tab->ctlo;
+    }
+    const int r0 = t.r0 + (w & 1) * 32, c0 = t.c0 + (w >> 1) * 32;
+    const int lr = lane & 15, kg = (lane >> 4) * 8;
+    const bool vec_ok = (K % 8) == 0;
+    float xs = 1.0f, inv_xs = 1.0f;
+    MapState& st = a.ms[t.m];
+    if (!SPLIT) {
+      const float amax = a.stage == 0 ? (float)sqrt(st.rr) * 1.0000001f : st.amax[a.stage];
+      xs = fp16_scale(amax);
+      inv_xs = 1.0f / xs;
+    }
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < K; k0 += 32) {
+      u16x8 bh[2], bl[2];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        bh[j] = load_t8(Bh, K, c0 + j * 16 + lr, k0 + kg, vec_ok);
+        if (SPLIT) bl[j] = load_t8(Bl, K, c0 + j * 16 + lr, k0 + kg, vec_ok);
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const f32x8 xv = load_x8(X, R, K, r0 + i * 16 + lr, k0 + kg, vec_ok);
+        if (SPLIT) {
+          bf16x8 xh, xl;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const __bf16 h = (__bf16)xv[e];
+            xh[e] = h;
+            xl[e] = (__bf16)(xv[e] - (float)h);
+          }
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            const bf16x8 ch = __builtin_bit_cast(bf16x8, bh[j]);
+            const bf16x8 cl = __builtin_bit_cast(bf16x8, bl[j]);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, ch, acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, cl, acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl, ch, acc[i][j], 0, 0, 0);
+          }
+        } else {
+          f16x8 xh;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) xh[e] = (_Float16)(xv[e] * xs);
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(xh, __builtin_bit_cast(f16x8, bh[j]),
+                                                               acc[i][j], 0, 0, 0);
+        }
+      }
+    }
+    // epilogue: lane holds D[row 4*(lane/16) + e][col lane mod 16] of each 16x16 tile
+    const MapDesc& d = a.desc[t.m];
+    const float* rv = reinterpret_cast<const float*>(a.rvec) + t.off;
+    const unsigned char* iso = (a.iso && d.use_iso) ? a.iso + t.off : nullptr;
+    double part = 0.0;
+    float vmax = 0.0f;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int c = c0 + j * 16 + lr;
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int rb = r0 + i * 16 + (lane >> 4) * 4;
+        float v[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int r = rb + e;
+          float y = acc[i][j][e] * inv_xs;
+          const bool in = c < K && r < R;
+          if (a.stage == 1 && in)
+            y = (c == 0 && r == 0) ? 0.0f
+                                   : (float)((double)y / (d.tabM->lam[c] + d.tabN->lam[r]));
+          if (a.stage == 3 && in) {
+            const size_t o = (size_t)c * R + r;
+            if (iso && iso[o]) y = 0.0f;
+            part += (double)rv[o] * (double)y;
+          }
+          v[e] = y;
+          if (in) vmax = fmaxf(vmax, fabsf(y));
+        }
+        if (c < K) {
+          if (rb + 3 < R && (R % 4) == 0) {
+            *reinterpret_cast<float4*>(Out + (size_t)c * R + rb) = make_float4(v[0], v[1], v[2], v[3]);
+          } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+              if (rb + e < R) Out[(size_t)c * R + rb + e] = v[e];
+          }
+        }
+      }
+    }
+    if (!SPLIT && a.stage < 3) {
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) vmax = fmaxf(vmax, __shfl_down(vmax, off, 64));
+      if (lane == 0)
+        atomicMax(reinterpret_cast<unsigned int*>(&st.amax[a.stage + 1]), __float_as_uint(vmax));
+    }
+    if (a.stage == 3) {
+      double vv[1] = {part};
+      block_sum<1>(vv, red);
+      if (threadIdx.x == 0) a.P[1 * a.pstride + g] = vv[0];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FMA stage (FP64 path, FP32 option): 64 x 64 tile, 16 x 16 threads x 4 x 4.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) k_e_dct_fma(DArgs a) {
+  __shared__ T Xs[16][64 + 4];
+  __shared__ T Bs[16][64 + 4];
+  __shared__ double red[4];
+  const int nact = a.counts[1];
+  const int tid = threadIdx.x, tr = tid % 16, tc = tid / 16;
+  const int lrow = tid / 4, lk = (tid % 4) * 4;
+  for (int t_ = blockIdx.x; t_ < nact; t_ += gridDim.x) {
+    const int g = a.dact[t_];
+    const DTile t = dtile(a, g);
+    if (!t.ok) continue;
+    const int R = t.R, K = t.K, r0 = t.r0, c0 = t.c0;
+    const T* X = reinterpret_cast<const T*>(a.X) + t.off;
+    T* Out = reinterpret_cast<T*>(a.Out) + t.off;
+    const T* B;
+    if (sizeof(T) == 8)
+      B = reinterpret_cast<const T*>(a.stage < 2 ? (const void*)t.tab->c64 : (const void*)t.tab->ct64);
+    else
+      B = reinterpret_cast<const T*>(a.stage < 2 ? (const void*)t.tab->c32 : (const void*)t.tab->ct32);
+    T acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = T(0);
+    for (int k0 = 0; k0 < K; k0 += 16) {
+      __syncthreads();
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int k = k0 + lk + e, rr = r0 + lrow, cc = c0 + lrow;
+        Xs[lk + e][lrow] = (rr < R && k < K) ? X[(size_t)rr * K + k] : T(0);
+        Bs[lk + e][lrow] = (cc < K && k < K) ? B[(size_t)cc * K + k] : T(0);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int kk = 0; kk < 16; ++kk) {
+        T xa[4], bb[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) xa[i] = Xs[kk][4 * tr + i];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) bb[j] = Bs[kk][4 * tc + j];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[i][j] += xa[i] * bb[j];
+      }
+    }
+    const MapDesc& d = a.desc[t.m];
+    const T* rv = reinterpret_cast<const T*>(a.rvec) + t.off;
+    const unsigned char* iso = (a.iso && d.use_iso) ? a.iso + t.off : nullptr;
+    double part = 0.0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int c = c0 + 4 * tc + j;
+      if (c >= K) continue;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = r0 + 4 * tr + i;
+        if (r >= R) continue;
+        const size_t o = (size_t)c * R + r;
+        T v = acc[i][j];
+        if (a.stage == 1) v = (c == 0 && r == 0) ? T(0) : (T)((double)v / (d.tabM->lam[c] + d.tabN->lam[r]));
+        if (a.stage == 3) {
+          if (iso && iso[o]) v = T(0);
+          part += (double)rv[o] * (double)v;
+        }
+        Out[o] = v;
+      }
+    }
+    if (a.stage == 3) {
+      double vv[1] = {part};
+      block_sum<1>(vv, red);
+      if (tid == 0) a.P[1 * a.pstride + g] = vv[0];
+    }
+    __syncthreads();
+  }
+}
+
+void e_dct_stage(hipStream_t st, const Engine& e, int ndtiles, int stage, int expect, int kind,
+                 const void* X, void* Out, const void* rvec) {
+  DArgs a;
+  a.desc = e.desc;
+  a.ms = e.ms;
+  a.dtile_map = e.dtile_map;
+  a.dact = e.dact;
+  a.counts = e.counts;
+  a.P = e.P;
+  a.pstride = e.pstride;
+  a.X = X;
+  a.Out = Out;
+  a.rvec = rvec;
+  a.iso = e.iso;
+  a.stage = stage;
+  a.expect = expect;
+  const int grid = std::max(1, std::min(ndtiles, 2048));
+  // kind: 0 FP64 FMA, 1 FP32 FMA, 2 split-bf16 MFMA, 3 scaled-fp16 MFMA
+  if (kind == 0) hipLaunchKernelGGL(k_e_dct_fma<double>, dim3(grid), dim3(256), 0, st, a);
+  else if (kind == 1) hipLaunchKernelGGL(k_e_dct_fma<float>, dim3(grid), dim3(256), 0, st, a);
+  else if (kind == 2) hipLaunchKernelGGL(k_e_dct_mfma<1>, dim3(grid), dim3(256), 0, st, a);
+  else hipLaunchKernelGGL(k_e_dct_mfma<0>, dim3(grid), dim3(256), 0, st, a);
+}
+
+// ---------------------------------------------------------------------------
+// Sweeps: one workgroup of 1024 threads per active map
+// ---------------------------------------------------------------------------
+constexpr int kSweepT = 1024;
+
+struct SArgs {
+  const MapDesc* desc;
+  MapState* ms;
+  const int* mact;
+  const int* counts;
+  double* P;
+  long long pstride;
+  const void *U, *V, *piv, *r;
+  void *s, *y;
+  int expect;
+  int ssor;
+  double omega;
+};
+
+// pivots: skewed wavefront, thread t owns row t of a chunk of rows
+template <typename T>
+__global__ void __launch_bounds__(kSweepT) k_e_pivots(SArgs a) {
+  extern __shared__ unsigned char smem_raw[];
+  if ((int)blockIdx.x >= a.counts[2]) return;
+  const int m = a.mact[blockIdx.x];
+  const MapDesc& d = a.desc[m];
+  const int M = d.M, N = d.N;
+  const T* U = reinterpret_cast<const T*>(a.U) + d.off;
+  const T* V = reinterpret_cast<const T*>(a.V) + d.off;
+  T* piv = reinterpret_cast<T*>(const_cast<void*>(a.piv)) + d.off;
+  T* prevrow = reinterpret_cast<T*>(smem_raw);
+  T* xch = prevrow + N;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  if (a.ssor) {
+    for (int p = tid; p < M * N; p += nt) {
+      const int i = p / N, j = p % N;
+      const T dg = (j > 0 ? U[p - 1] : T(0)) + U[p] + (i > 0 ? V[p - N] : T(0)) + V[p];
+      piv[p] = dg == T(0) ? T(1) : dg / (T)a.omega;
+    }
+    return;
+  }
+  for (int rb = 0; rb < M; rb += nt) {
+    const int rows = min(nt, M - rb);
+    const int i = rb + tid;
+    T pleft = T(1), uleft = T(0);
+    const int steps = rows + N - 1;
+    for (int s = 0; s < steps; ++s) {
+      const int j = s - tid;
+      T pv = T(0);
+      if (tid < rows && j >= 0 && j < N) {
+        const size_t p = (size_t)i * N + j;
+        const T uc = U[p], vc = V[p];
+        const T vn = (i > 0) ? V[p - N] : T(0);
+        const T av = uleft + uc + vn + vc;
+        if (av == T(0)) {
+          pv = T(1);
+        } else {
+          T v = av;
+          if (j > 0) v -= uleft * uleft / pleft;
+          if (i > 0) {
+            const T pup = (tid == 0) ? prevrow[j] : xch[((s - 1) & 1) * nt + tid - 1];
+            v -= vn * vn / pup;
+          }
+          if (v < (T)kPivotFloor * av) v = av;
+          pv = v;
+        }
+        piv[p] = pv;
+        pleft = pv;
+        uleft = uc;
+        if (tid == nt - 1) prevrow[j] = pv;
+      }
+      xch[(s & 1) * nt + tid] = pv;
+      __syncthreads();
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T, bool REV>
+__device__ __forceinline__ T block_affine_excl(T A, T C, T* sA, T* sC) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const T Ap = REV ? __shfl_down(A, off, 64) : __shfl_up(A, off, 64);
+    const T Cp = REV ? __shfl_down(C, off, 64) : __shfl_up(C, off, 64);
+    const bool has = REV ? (lane + off < 64) : (lane >= off);
+    if (has) {
+      A = A + C * Ap;
+      C = C * Cp;
+    }
+  }
+  T Ae = REV ? __shfl_down(A, 1, 64) : __shfl_up(A, 1, 64);
+  T Ce = REV ? __shfl_down(C, 1, 64) : __shfl_up(C, 1, 64);
+  if (REV ? (lane == 63) : (lane == 0)) {
+    Ae = T(0);
+    Ce = T(1);
+  }
+  __syncthreads();
+  if (REV ? (lane == 0) : (lane == 63)) {
+    sA[w] = A;
+    sC[w] = C;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    T aa = T(0), cc = T(1);
+    for (int k = 0; k < nw; ++k) {
+      const int ww = REV ? (nw - 1 - k) : k;
+      const T ta = sA[ww], tc = sC[ww];
+      sA[ww] = aa;
+      sC[ww] = cc;
+      aa = ta + tc * aa;
+      cc = tc * cc;
+    }
+  }
+  __syncthreads();
+  return Ae + Ce * sA[w];
+}
+
+// forward (P + L) y = r, backward (P + L^T) z = P y, s = scale z; partial r.s
+template <typename T, int EPT>
+__global__ void __launch_bounds__(kSweepT) k_e_sweep(SArgs a) {
+  __shared__ T sA[kSweepT / 64], sC[kSweepT / 64];
+  __shared__ double red[kSweepT / 64];
+  if ((int)blockIdx.x >= a.counts[2]) return;
+  const int m = a.mact[blockIdx.x];
+  if (a.expect >= 0 && a.ms[m].state != a.expect) return;
+  const MapDesc& d = a.desc[m];
+  const int M = d.M, N = d.N;
+  const T* U = reinterpret_cast<const T*>(a.U) + d.off;
+  const T* V = reinterpret_cast<const T*>(a.V) + d.off;
+  const T* piv = reinterpret_cast<const T*>(a.piv) + d.off;
+  const T* r = reinterpret_cast<const T*>(a.r) + d.off;
+  T* s = reinterpret_cast<T*>(a.s) + d.off;
+  T* y = reinterpret_cast<T*>(a.y) + d.off;
+  const T scale = a.ssor ? (T)(2.0 - a.omega) : T(1);
+  const int j0 = threadIdx.x * EPT;
+  T prev[EPT];
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) prev[e] = T(0);
+  for (int i = 0; i < M; ++i) {
+    T av[EPT], cv[EPT];
+    T SA = T(0), SC = T(1);
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int j = j0 + e;
+      if (j < N) {
+        const size_t p = (size_t)i * N + j;
+        const T pp = piv[p];
+        const T vn = i > 0 ? V[p - N] : T(0);
+        const T uw = j > 0 ? U[p - 1] : T(0);
+        av[e] = (r[p] + vn * prev[e]) / pp;
+        cv[e] = uw / pp;
+      } else {
+        av[e] = T(0);
+        cv[e] = T(0);
+      }
+      SA = av[e] + cv[e] * SA;
+      SC = cv[e] * SC;
+    }
+    T yin = block_affine_excl<T, false>(SA, SC, sA, sC);
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      yin = av[e] + cv[e] * yin;
+      prev[e] = yin;
+      if (j0 + e < N) y[(size_t)i * N + j0 + e] = yin;
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) prev[e] = T(0);
+  double part = 0.0;
+  for (int i = M - 1; i >= 0; --i) {
+    T av[EPT], cv[EPT];
+    T SA = T(0), SC = T(1);
+#pragma unroll
+    for (int e = EPT - 1; e >= 0; --e) {
+      const int j = j0 + e;
+      if (j < N) {
+        const size_t p = (size_t)i * N + j;
+        const T pp = piv[p];
+        av[e] = y[p] + V[p] * prev[e] / pp;
+        cv[e] = U[p] / pp;
+      } else {
+        av[e] = T(0);
+        cv[e] = T(0);
+      }
+      SA = av[e] + cv[e] * SA;
+      SC = cv[e] * SC;
+    }
+    T zin = block_affine_excl<T, true>(SA, SC, sA, sC);
+#pragma unroll
+    for (int e = EPT - 1; e >= 0; --e) {
+      const int j = j0 + e;
+      zin = av[e] + cv[e] * zin;
+      prev[e] = zin;
+      if (j < N) {
+        const size_t p = (size_t)i * N + j;
+        const T sv = scale * zin;
+        s[p] = sv;
+        part += (double)r[p] * (double)sv;
+      }
+    }
+  }
+  double v[1] = {part};
+  block_sum<1>(v, red);
+  if (threadIdx.x == 0) a.P[1 * a.pstride + d.dtile0] = v[0];
+}
+
+static SArgs make_sargs(const Engine& e, int expect, bool ssor, double omega, const void* r,
+                        void* s, void* y) {
+  SArgs a;
+  a.desc = e.desc;
+  a.ms = e.ms;
+  a.mact = e.mact;
+  a.counts = e.counts;
+  a.P = e.P;
+  a.pstride = e.pstride;
+  a.U = e.U;
+  a.V = e.V;
+  a.piv = e.aux;
+  a.r = r;
+  a.s = s;
+  a.y = y;
+  a.expect = expect;
+  a.ssor = ssor ? 1 : 0;
+  a.omega = omega;
+  return a;
+}
+
+template <typename T>
+void e_pivots(hipStream_t st, const Engine& e, int nmaps, int maxN, bool ssor, double omega) {
+  const size_t shm = (size_t)maxN * sizeof(T) + 2 * kSweepT * sizeof(T);
+  hipLaunchKernelGGL(k_e_pivots<T>, dim3(std::max(1, nmaps)), dim3(kSweepT), shm, st,
+                     make_sargs(e, -1, ssor, omega, nullptr, nullptr, nullptr));
+}
+
+template <typename T>
+void e_sweep(hipStream_t st, const Engine& e, int nmaps, int maxN, int expect, bool ssor,
+             double omega, const void* r, void* s, void* y) {
+  const SArgs a = make_sargs(e, expect, ssor, omega, r, s, y);
+  const int ept = (maxN + kSweepT - 1) / kSweepT;
+  const dim3 g(std::max(1, nmaps));
+  if (ept <= 1) hipLaunchKernelGGL((k_e_sweep<T, 1>), g, dim3(kSweepT), 0, st, a);
+  else if (ept <= 2) hipLaunchKernelGGL((k_e_sweep<T, 2>), g, dim3(kSweepT), 0, st, a);
+  else hipLaunchKernelGGL((k_e_sweep<T, 4>), g, dim3(kSweepT), 0, st, a);
+}
+
+template void e_pivots<float>(hipStream_t, const Engine&, int, int, bool, double);
+template void e_pivots<double>(hipStream_t, const Engine&, int, int, bool, double);
+template void e_sweep<float>(hipStream_t, const Engine&, int, int, int, bool, double, const void*,
+                             void*, void*);
+template void e_sweep<double>(hipStream_t, const Engine&, int, int, int, bool, double, const void*,
+                              void*, void*);
+
+}  // namespace lpu

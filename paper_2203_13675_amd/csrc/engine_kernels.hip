@@ -1,0 +1,786 @@
+// Batched kernels of the phase-unwrapping PCG (gfx950).
+//
+// Stencil tiles are 128 columns x 16 rows, one 64-lane wave each: lane l owns
+// columns j0 + l and j0 + 64 + l (two coalesced 64-wide rows per load), the
+// wave marches down the 16 rows keeping rows i-1, i, i+1 of the operand in
+// registers, and horizontal neighbours come from lane shuffles (plus one halo
+// column at each side, loaded by lanes 0 and 63).  Each tile writes its FP64
+// partial sums to its own slot; finisher kernels reduce per map.
+//
+// The operator is Eq. (7):
+//   (A x)_{i,j} = (U_{i,j-1} + U_{i,j} + V_{i-1,j} + V_{i,j}) x_{i,j}
+//               - U_{i,j} x_{i,j+1} - U_{i,j-1} x_{i,j-1}
+//               - V_{i,j} x_{i+1,j} - V_{i-1,j} x_{i-1,j},
+// out-of-grid terms zero (U is 0 on the last column, V on the last row).
+
+#include "lpu_internal.h"
+#include "lpu_device.h"
+
+namespace lpu {
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+template <typename T>
+struct R2 {
+  T a, b;  // columns j0 + lane, j0 + 64 + lane
+};
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+template <typename T>
+__device__ __forceinline__ T shup(T v) { return __shfl_up(v, 1, 64); }
+template <typename T>
+__device__ __forceinline__ T shdn(T v) { return __shfl_down(v, 1, 64); }
+template <typename T>
+__device__ __forceinline__ T shfrom(T v, int src) { return __shfl(v, src, 64); }
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+struct TilePos {
+  int m, i0, j0, M, N;
+  long long off;
+};
+
+__device__ __forceinline__ TilePos tile_pos(const MapDesc* __restrict__ desc,
+                                            const int* __restrict__ tile_map, int g) {
+  TilePos t;
+  t.m = tile_map[g];
+  const MapDesc& d = desc[t.m];
+  const int lt = g - d.tile0;
+  const int ty = lt / d.tiles_x;
+  t.i0 = ty * kTH;
+  t.j0 = (lt - ty * d.tiles_x) * kTW;
+  t.M = d.M;
+  t.N = d.N;
+  t.off = d.off;
+  return t;
+}
+
+// left/right neighbours of a row pair (lane shuffles + halo values)
+template <typename T>
+__device__ __forceinline__ void neighbours(const R2<T>& v, T halo, R2<T>& w, R2<T>& e) {
+  const int l = lane_id();
+  const T up_a = shup(v.a), up_b = shup(v.b);
+  const T dn_a = shdn(v.a), dn_b = shdn(v.b);
+  const T a63 = shfrom(v.a, 63), b0 = shfrom(v.b, 0);
+  const T h0 = shfrom(halo, 0), h63 = shfrom(halo, 63);
+  w.a = l > 0 ? up_a : h0;     // column j0 - 1 for lane 0
+  w.b = l > 0 ? up_b : a63;    // column j0 + 63 for lane 0
+  e.a = l < 63 ? dn_a : b0;    // column j0 + 64 for lane 63
+  e.b = l < 63 ? dn_b : h63;   // column j0 + 128 for lane 63
+}
+
+template <typename T>
+__device__ __forceinline__ T ldz(const T* __restrict__ a, int i, int j, int M, int N) {
+  return (i >= 0 && i < M && j >= 0 && j < N) ? a[(size_t)i * N + j] : T(0);
+}
+
+template <typename T>
+__device__ __forceinline__ R2<T> ldrow(const T* __restrict__ a, int i, int j0, int M, int N) {
+  const int l = lane_id();
+  R2<T> v;
+  v.a = ldz(a, i, j0 + l, M, N);
+  v.b = ldz(a, i, j0 + 64 + l, M, N);
+  return v;
+}
+
+// halo column of this lane (lane 0: j0 - 1, lane 63: j0 + 128, others none)
+__device__ __forceinline__ int halo_col(int j0) {
+  const int l = lane_id();
+  return l == 0 ? j0 - 1 : (l == 63 ? j0 + kTW : -1);
+}
+
+template <typename T>
+__device__ __forceinline__ T stencil5(T uw, T uc, T vn, T vc, T xc, T xw, T xe, T xn, T xs) {
+  return (uw + uc + vn + vc) * xc - uc * xe - uw * xw - vc * xs - vn * xn;
+}
+
+// March the tile: for every interior pixel call epi(i, j, x_ij, (A x)_ij),
+// where the operand x is given by field(i, j) (zero outside the grid).
+template <typename T, typename F, typename E>
+__device__ __forceinline__ void march_stencil(const TilePos& tp, const T* __restrict__ U,
+                                              const T* __restrict__ V, F field, E epi) {
+  const int M = tp.M, N = tp.N, i0 = tp.i0, j0 = tp.j0, l = lane_id();
+  const int hj = halo_col(j0);
+  const int ca = j0 + l, cb = j0 + 64 + l;
+  auto frow = [&](int i) {
+    R2<T> v;
+    v.a = field(i, ca);
+    v.b = field(i, cb);
+    return v;
+  };
+  R2<T> xm = frow(i0 - 1), xc = frow(i0);
+  T xh = field(i0, hj);
+  R2<T> vn = ldrow(V, i0 - 1, j0, M, N);
+#pragma unroll 4
+  for (int k = 0; k < kTH; ++k) {
+    const int i = i0 + k;
+    if (i >= M) break;
+    const R2<T> xp = frow(i + 1);
+    const T xph = field(i + 1, hj);
+    const R2<T> uc = ldrow(U, i, j0, M, N);
+    const T uh = (l == 0) ? ldz(U, i, j0 - 1, M, N) : T(0);
+    const R2<T> vc = ldrow(V, i, j0, M, N);
+    R2<T> xw, xe, uw, ue;
+    neighbours(xc, xh, xw, xe);
+    neighbours(uc, uh, uw, ue);
+    if (ca < N)
+      epi(i, ca, xc.a, stencil5<T>(uw.a, uc.a, vn.a, vc.a, xc.a, xw.a, xe.a, xm.a, xp.a));
+    if (cb < N)
+      epi(i, cb, xc.b, stencil5<T>(uw.b, uc.b, vn.b, vc.b, xc.b, xw.b, xe.b, xm.b, xp.b));
+    xm = xc;
+    xc = xp;
+    xh = xph;
+    vn = vc;
+  }
+}
+
+// Elementwise walk over the tile's pixels.
+template <typename E>
+__device__ __forceinline__ void march_points(const TilePos& tp, E epi) {
+  const int l = lane_id();
+  for (int k = 0; k < kTH; ++k) {
+    const int i = tp.i0 + k;
+    if (i >= tp.M) break;
+    const int ca = tp.j0 + l, cb = tp.j0 + 64 + l;
+    if (ca < tp.N) epi(i, ca);
+    if (cb < tp.N) epi(i, cb);
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ T* vec(void* base, long long off) {
+  return reinterpret_cast<T*>(base) + off;
+}
+template <typename T>
+__device__ __forceinline__ const T* cvec(const void* base, long long off) {
+  return reinterpret_cast<const T*>(base) + off;
+}
+
+// Kernel arguments shared by the tile kernels.
+struct EArgs {
+  const MapDesc* desc;
+  MapState* ms;
+  const int* tile_map;
+  const int* act;
+  const int* counts;
+  double* P;
+  long long pstride;
+  void *U, *V, *aux, *x0, *x1, *d0, *d1, *r, *s, *q, *b;
+  double *dx, *dy, *phi_prev, *r64;
+  const unsigned char* iso;
+};
+
+#define TILE_LOOP(A)                                                  \
+  const int n_act_ = (A).counts[0];                                   \
+  for (int t_ = blockIdx.x; t_ < n_act_; t_ += gridDim.x)
+
+// ---------------------------------------------------------------------------
+// Set-up kernels: wrapped differences, weights, Jacobi diagonal, isolation
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wrap_w(double x) {
+#pragma clang fp contract(off)
+  const double k = ceil((x - kPi) / kTwoPi);
+  return x - kTwoPi * k;
+}
+
+__global__ void __launch_bounds__(64) k_e_wrapdiff(EArgs A) {
+  TILE_LOOP(A) {
+    const int g = A.act[t_];
+    const TilePos tp = tile_pos(A.desc, A.tile_map, g);
+    const double* psi = A.desc[tp.m].psi;
+    double* dx = A.dx + tp.off;
+    double* dy = A.dy + tp.off;
+    march_points(tp, [&](int i, int j) {
+      const size_t p = (size_t)i * tp.N + j;
+      const double c = psi[p];
+      dx[p] = (j < tp.N - 1) ? wrap_w(psi[p + 1] - c) : 0.0;
+      dy[p] = (i < tp.M - 1) ? wrap_w(psi[p + tp.N] - c) : 0.0;
+    });
+  }
+}
+
+__device__ __forceinline__ double abs_pow(double r, double e) {
+  if (e == 2.0) return r * r;
+  if (e == 1.0) return fabs(r);
+  if (e == 0.0) return 1.0;
+  return pow(fabs(r), e);
+}
+
+// U, V of Eq. (6) from phi (FP64), stored as T; also the Jacobi inverse
+// diagonal needs U, V of neighbours, so it is a separate pass.
+template <typename T>
+__global__ void __launch_bounds__(64) k_e_weights(EArgs A, double e, double tau) {
+  TILE_LOOP(A) {
+    const int g = A.act[t_];
+    const TilePos tp = tile_pos(A.desc, A.tile_map, g);
+    const MapDesc& d = A.desc[tp.m];
+    const double* phi = d.phi;
+    const float* mask = d.mask;
+    const double* dx = A.dx + tp.off;
+    const double* dy = A.dy + tp.off;
+    T* U = vec<T>(A.U, tp.off);
+    T* V = vec<T>(A.V, tp.off);
+    march_points(tp, [&](int i, int j) {
+      const size_t p = (size_t)i * tp.N + j;
+      const double c = phi[p];
+      double u = 0.0, v = 0.0;
+      if (j < tp.N - 1) {
+        const double r = phi[p + 1] - c - dx[p];
+        const double w = mask ? (double)fminf(mask[p], mask[p + 1]) : 1.0;
+        u = w * (tau / (abs_pow(r, e) + tau));
+      }
+      if (i < tp.M - 1) {
+        const double r = phi[p + tp.N] - c - dy[p];
+        const double w = mask ? (double)fminf(mask[p], mask[p + tp.N]) : 1.0;
+        v = w * (tau / (abs_pow(r, e) + tau));
+      }
+      U[p] = (T)u;
+      V[p] = (T)v;
+    });
+  }
+}
+
+// Jacobi inverse diagonal (0 on isolated pixels) and isolation flags.
+template <typename T>
+__global__ void __launch_bounds__(64) k_e_diag(EArgs A, int want_inv) {
+  TILE_LOOP(A) {
+    const int g = A.act[t_];
+    const TilePos tp = tile_pos(A.desc, A.tile_map, g);
+    const T* U = cvec<T>(A.U, tp.off);
+    const T* V = cvec<T>(A.V, tp.off);
+    T* inv = vec<T>(A.aux, tp.off);
+    unsigned char* iso = const_cast<unsigned char*>(A.iso) + tp.off;
+    march_points(tp, [&](int i, int j) {
+      const size_t p = (size_t)i * tp.N + j;
+      const T dg = ldz(U, i, j - 1, tp.M, tp.N) + U[p] + ldz(V, i - 1, j, tp.M, tp.N) + V[p];
+      if (want_inv) inv[p] = dg > T(0) ? T(1) / dg : T(0);
+      iso[p] = dg == T(0) ? 1 : 0;
+    });
+  }
+}
+
+// ---------------------------------------------------------------------------
+// b = D^T W Delta and r64 = b - A phi (FP64; r formed as D^T W (Delta - D phi)).
+// mode 0: b as T and as FP64 in r64 (phi unused); mode 1: r64 and (T) r64 into b;
+// mode 2: r64 only.  Partials: slot 0 = r.r (mode 0: b.b), slot 1 = b.b.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(64) k_e_rhs(EArgs A, int mode) {
+  TILE_LOOP(A) {
+    const int g = A.act[t_];
+    const TilePos tp = tile_pos(A.desc, A.tile_map, g);
+    const MapDesc& d = A.desc[tp.m];
+    const T* U = cvec<T>(A.U, tp.off);
+    const T* V = cvec<T>(A.V, tp.off);
+    const double* dx = A.dx + tp.off;
+    const double* dy = A.dy + tp.off;
+    const double* phi = d.phi;
+    T* bT = vec<T>(A.b, tp.off);
+    double* r64 = A.r64 + tp.off;
+    const int M = tp.M, N = tp.N;
+    double srr = 0.0, sbb = 0.0;
+    march_points(tp, [&](int i, int j) {
+      const size_t p = (size_t)i * N + j;
+      const bool usephi = mode != 0;
+      const double pc = usephi ? phi[p] : 0.0;
+      double hx = 0.0, hy = 0.0, bx = 0.0, by = 0.0, hxw = 0.0, hyn = 0.0, bxw = 0.0, byn = 0.0;
+      if (j < N - 1) {
+        const double u = (double)U[p];
+        bx = u * dx[p];
+        hx = usephi ? u * (dx[p] - (phi[p + 1] - pc)) : bx;
+      }
+      if (i < M - 1) {
+        const double v = (double)V[p];
+        by = v * dy[p];
+        hy = usephi ? v * (dy[p] - (phi[p + N] - pc)) : by;
+      }
+      if (j > 0) {
+        const double u = (double)U[p - 1];
+        bxw = u * dx[p - 1];
+        hxw = usephi ? u * (dx[p - 1] - (pc - phi[p - 1])) : bxw;
+      }
+      if (i > 0) {
+        const double v = (double)V[p - N];
+        byn = v * dy[p - N];
+        hyn = usephi ? v * (dy[p - N] - (pc - phi[p - N])) : byn;
+      }
+      const double b = bxw + byn - bx - by;
+      const double r = hxw + hyn - hx - hy;
+      if (mode == 0) bT[p] = (T)b;
+      if (mode == 1) bT[p] = (T)r;
+      r64[p] = mode == 0 ? b : r;
+      srr += r * r;
+      sbb += b * b;
+    });
+    srr = wave_sum(srr);
+    sbb = wave_sum(sbb);
+    if (lane_id() == 0) {
+      A.P[0 * A.pstride + g] = srr;
+      A.P[1 * A.pstride + g] = sbb;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Small per-tile passes used by the outer loop
+// ---------------------------------------------------------------------------
+// op 0: phi_prev = phi; op 1: x0 = phi (T); op 2: x0 = 0;
+// op 3: phi += x_final (x buffer chosen by the map's l); op 4: partials of
+// ||phi - phi_prev||^2 (slot 0) and ||phi_prev||^2 (slot 1);
+// op 5: phi = x_final (FP64 path).
+template <typename T>
+__global__ void __launch_bounds__(64) k_e_pass(EArgs A, int op) {
+  TILE_LOOP(A) {
+    const int g = A.act[t_];
+    const TilePos tp = tile_pos(A.desc, A.tile_map, g);
+    double* phi = A.desc[tp.m].phi;
+    double* pp = A.phi_prev + tp.off;
+    const long long l = A.ms[tp.m].l;
+    T* x0 = vec<T>(A.x0, tp.off);
+    const T* xf = cvec<T>((l & 1) ? A.x1 : A.x0, tp.off);
+    double s0 = 0.0, s1 = 0.0;
+    march_points(tp, [&](int i, int j) {
+      const size_t p = (size_t)i * tp.N + j;
+      switch (op) {
+        case 0: pp[p] = phi[p]; break;
+        case 1: x0[p] = (T)phi[p]; break;
+        case 2: x0[p] = T(0); break;
+        case 3: phi[p] += (double)xf[p]; break;
+        case 4: {
+          const double dd = phi[p] - pp[p];
+          s0 += dd * dd;
+          s1 += pp[p] * pp[p];
+        } break;
+        case 5: phi[p] = (double)xf[p]; break;
+      }
+    });
+    if (op == 4) {
+      s0 = wave_sum(s0);
+      s1 = wave_sum(s1);
+      if (lane_id() == 0) {
+        A.P[0 * A.pstride + g] = s0;
+        A.P[1 * A.pstride + g] = s1;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// PCG tile kernels
+// ---------------------------------------------------------------------------
+// init: r = b - A x0, d_old(parity 0) = 0, pointwise s; partials r.r, r.s, b.b
+// confirm (CONF = 1): r = b - A x (current parity), pointwise s; partials r.r, r.s
+template <typename T, int PC, int CONF>
+__global__ void __launch_bounds__(64) k_e_resid(EArgs A) {
+  TILE_LOOP(A) {
+    const int g = A.act[t_];
+    const TilePos tp = tile_pos(A.desc, A.tile_map, g);
+    const MapState& st = A.ms[tp.m];
+    if (st.state != (CONF ? kConfirm : kRun)) continue;
+    const long long l = st.l;
+    const T* U = cvec<T>(A.U, tp.off);
+    const T* V = cvec<T>(A.V, tp.off);
+    const T* aux = cvec<T>(A.aux, tp.off);
+    const T* b = cvec<T>(A.b, tp.off);
+    const T* x = cvec<T>(CONF && (l & 1) ? A.x1 : A.x0, tp.off);
+    T* r = vec<T>(A.r, tp.off);
+    T* d0 = vec<T>(A.d0, tp.off);
+    const int M = tp.M, N = tp.N;
+    double srr = 0.0, srs = 0.0, sbb = 0.0;
+    march_stencil<T>(tp, U, V, [&](int i, int j) { return ldz(x, i, j, M, N); },
+                     [&](int i, int j, T, T ax) {
+                       const size_t p = (size_t)i * N + j;
+                       const T bv = b[p];
+                       const T rv = bv - ax;
+                       r[p] = rv;
+                       if (!CONF) d0[p] = T(0);
+                       const T sv = PC == kPcJacobi ? rv * aux[p] : rv;
+                       srr += (double)rv * (double)rv;
+                       srs += (double)rv * (double)sv;
+                       sbb += (double)bv * (double)bv;
+                     });
+    srr = wave_sum(srr);
+    srs = wave_sum(srs);
+    sbb = wave_sum(sbb);
+    if (lane_id() == 0) {
+      A.P[0 * A.pstride + g] = srr;
+      A.P[1 * A.pstride + g] = srs;
+      A.P[2 * A.pstride + g] = sbb;
+    }
+  }
+}
+
+// spmv: d_new = s + beta d_old; q = A d_new; partial d^T q
+template <typename T, int PC>
+__global__ void __launch_bounds__(64) k_e_spmv(EArgs A) {
+  TILE_LOOP(A) {
+    const int g = A.act[t_];
+    const TilePos tp = tile_pos(A.desc, A.tile_map, g);
+    const MapState& st = A.ms[tp.m];
+    if (st.state != kRun) continue;
+    const long long l = st.l;
+    const T beta = (T)st.beta;
+    const T* U = cvec<T>(A.U, tp.off);
+    const T* V = cvec<T>(A.V, tp.off);
+    const T* aux = cvec<T>(A.aux, tp.off);
+    const T* src = cvec<T>(PC == kPcNone || PC == kPcJacobi ? A.r : A.s, tp.off);
+    const T* dold = cvec<T>((l & 1) ? A.d1 : A.d0, tp.off);
+    T* dnew = vec<T>((l & 1) ? A.d0 : A.d1, tp.off);
+    T* q = vec<T>(A.q, tp.off);
+    const int M = tp.M, N = tp.N;
+    double sdq = 0.0;
+    march_stencil<T>(
+        tp, U, V,
+        [&](int i, int j) {
+          if (i < 0 || i >= M || j < 0 || j >= N) return T(0);
+          const size_t p = (size_t)i * N + j;
+          const T sv = PC == kPcJacobi ? src[p] * aux[p] : src[p];
+          return sv + beta * dold[p];
+        },
+        [&](int i, int j, T dv, T qv) {
+          const size_t p = (size_t)i * N + j;
+          dnew[p] = dv;
+          q[p] = qv;
+          sdq += (double)dv * (double)qv;
+        });
+    sdq = wave_sum(sdq);
+    if (lane_id() == 0) A.P[0 * A.pstride + g] = sdq;
+  }
+}
+
+// update: x_new = x_old + alpha d; r -= alpha q, or r = b - A x_new when
+// l is a multiple of the replacement period; pointwise s; partials r.r, r.s
+template <typename T, int PC>
+__global__ void __launch_bounds__(64) k_e_update(EArgs A) {
+  TILE_LOOP(A) {
+    const int g = A.act[t_];
+    const TilePos tp = tile_pos(A.desc, A.tile_map, g);
+    const MapState& st = A.ms[tp.m];
+    if (st.state != kRun) continue;
+    const long long l = st.l;
+    const T alpha = (T)st.alpha;
+    const bool replace = (l % st.period) == 0;
+    const T* U = cvec<T>(A.U, tp.off);
+    const T* V = cvec<T>(A.V, tp.off);
+    const T* aux = cvec<T>(A.aux, tp.off);
+    const T* b = cvec<T>(A.b, tp.off);
+    const T* xold = cvec<T>((l & 1) ? A.x1 : A.x0, tp.off);
+    T* xnew = vec<T>((l & 1) ? A.x0 : A.x1, tp.off);
+    const T* d = cvec<T>((l & 1) ? A.d0 : A.d1, tp.off);
+    const T* q = cvec<T>(A.q, tp.off);
+    T* r = vec<T>(A.r, tp.off);
+    const int M = tp.M, N = tp.N;
+    double srr = 0.0, srs = 0.0;
+    if (replace) {
+      march_stencil<T>(
+          tp, U, V,
+          [&](int i, int j) {
+            if (i < 0 || i >= M || j < 0 || j >= N) return T(0);
+            const size_t p = (size_t)i * N + j;
+            return xold[p] + alpha * d[p];
+          },
+          [&](int i, int j, T xv, T ax) {
+            const size_t p = (size_t)i * N + j;
+            const T rv = b[p] - ax;
+            xnew[p] = xv;
+            r[p] = rv;
+            const T sv = PC == kPcJacobi ? rv * aux[p] : rv;
+            srr += (double)rv * (double)rv;
+            srs += (double)rv * (double)sv;
+          });
+    } else {
+      march_points(tp, [&](int i, int j) {
+        const size_t p = (size_t)i * N + j;
+        xnew[p] = xold[p] + alpha * d[p];
+        const T rv = r[p] - alpha * q[p];
+        r[p] = rv;
+        const T sv = PC == kPcJacobi ? rv * aux[p] : rv;
+        srr += (double)rv * (double)rv;
+        srs += (double)rv * (double)sv;
+      });
+    }
+    srr = wave_sum(srr);
+    srs = wave_sum(srs);
+    if (lane_id() == 0) {
+      A.P[0 * A.pstride + g] = srr;
+      A.P[1 * A.pstride + g] = srs;
+    }
+  }
+}
+
+// y = A x for the step entry point (x in A.s, y in A.q)
+template <typename T>
+__global__ void __launch_bounds__(64) k_e_apply(EArgs A) {
+  TILE_LOOP(A) {
+    const int g = A.act[t_];
+    const TilePos tp = tile_pos(A.desc, A.tile_map, g);
+    const T* U = cvec<T>(A.U, tp.off);
+    const T* V = cvec<T>(A.V, tp.off);
+    const T* x = cvec<T>(A.s, tp.off);
+    T* y = vec<T>(A.q, tp.off);
+    const int M = tp.M, N = tp.N;
+    march_stencil<T>(tp, U, V, [&](int i, int j) { return ldz(x, i, j, M, N); },
+                     [&](int i, int j, T, T ax) { y[(size_t)i * N + j] = ax; });
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Finisher: one block per map, fixed-order sums of the map's partials, then
+// the map's PCG state advances.
+// ---------------------------------------------------------------------------
+enum FinOp : int {
+  kFinInit = 0,     // slots 0,1,2 over stencil tiles: r.r, r.s, b.b
+  kFinAlpha = 1,    // slot 0: d^T q
+  kFinUpdate = 2,   // slots 0,1: r.r, r.s
+  kFinConfirm = 3,  // slots 0,1: r.r, r.s
+  kFinTail = 4,     // slot 1 over DCT tiles (or one sweep partial): r.s
+  kFinSum2 = 5      // slots 0,1 over stencil tiles -> rr, bb (no state change)
+};
+
+__device__ inline void map_finish(MapState& s, int mode, double rs) {
+  if (mode == kFinishIter) {
+    s.delta_old = s.delta_new;
+    s.delta_new = rs;
+    s.beta = rs / s.delta_old;
+    s.l += 1;
+  } else if (mode == kFinishConfirm) {
+    s.delta_new = rs;
+    s.beta = rs / s.delta_old;
+  } else {
+    s.delta_new = rs;
+    s.delta0 = rs;
+    s.beta = 0.0;
+    s.thr_delta = s.eps2 * rs;
+  }
+  s.nfinish += 1;
+  int st = kRun;
+  if (s.rule == LPU_STOP_PAPER) {
+    if (!(s.delta_new > s.thr_delta)) st = kDone;
+  } else if (s.rr <= s.thr_rr && (s.replaced || mode != kFinishIter)) {
+    st = kDone;
+  }
+  if (st == kRun) {
+    if (!isfinite(s.delta_new) || s.delta_new < 0.0 || !isfinite(s.beta)) st = kBreakdown;
+    else if (s.l >= s.l_max) st = kCap;
+  }
+  s.state = st;
+}
+
+template <int NS>
+__device__ __forceinline__ void fin_sums(const double* __restrict__ P, long long pstride, int first,
+                                         int count, const int* slots, double (&out)[NS],
+                                         double* smem) {
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    double v = 0.0;
+    for (int t = threadIdx.x; t < count; t += blockDim.x) v += P[slots[k] * pstride + first + t];
+    out[k] = v;
+  }
+  block_sum<NS>(out, smem);
+}
+
+__global__ void __launch_bounds__(256) k_e_finish(const MapDesc* __restrict__ desc, MapState* ms,
+                                                  const double* __restrict__ P, long long pstride,
+                                                  int op, int expect, int mode, int pointwise,
+                                                  int tail_single) {
+  __shared__ double red[3 * 4];
+  const int m = blockIdx.x;
+  MapState& s = ms[m];
+  if (expect >= 0 && s.state != expect) return;
+  const MapDesc& d = desc[m];
+  double v[3] = {0.0, 0.0, 0.0};
+  if (op == kFinInit) {
+    const int sl[3] = {0, 1, 2};
+    fin_sums<3>(P, pstride, d.tile0, d.ntiles, sl, v, red);
+  } else if (op == kFinAlpha) {
+    const int sl[1] = {0};
+    double w[1];
+    fin_sums<1>(P, pstride, d.tile0, d.ntiles, sl, w, red);
+    v[0] = w[0];
+  } else if (op == kFinTail) {
+    const int sl[1] = {1};
+    double w[1];
+    fin_sums<1>(P, pstride, d.dtile0, tail_single ? 1 : d.ndt, sl, w, red);
+    v[0] = w[0];
+  } else {
+    const int sl[2] = {0, 1};
+    double w[2];
+    fin_sums<2>(P, pstride, d.tile0, d.ntiles, sl, w, red);
+    v[0] = w[0];
+    v[1] = w[1];
+  }
+  if (threadIdx.x != 0) return;
+  switch (op) {
+    case kFinInit:
+      s.rr = v[0];
+      s.bb = v[2];
+      s.thr_rr = s.tol2 * v[2];
+      s.l = 0;
+      s.replaced = 1;
+      if (v[2] == 0.0) s.state = kDone;
+      else if (pointwise) map_finish(s, kFinishInit, v[1]);
+      else s.state = kInitPc;
+      break;
+    case kFinAlpha:
+      s.dq = v[0];
+      if (!(v[0] > 0.0) || !isfinite(v[0])) s.state = kBreakdown;
+      else s.alpha = s.delta_new / v[0];
+      break;
+    case kFinUpdate: {
+      const bool replace = (s.l % s.period) == 0;
+      s.rr = v[0];
+      s.replaced = replace ? 1 : 0;
+      if (s.rule == LPU_STOP_RELRES && !replace && v[0] <= s.thr_rr) {
+        s.delta_old = s.delta_new;
+        s.l += 1;
+        s.state = kConfirm;
+      } else if (pointwise) {
+        map_finish(s, kFinishIter, v[1]);
+      }
+    } break;
+    case kFinConfirm:
+      s.rr = v[0];
+      s.replaced = 1;
+      if (v[0] <= s.thr_rr) s.state = kDone;
+      else if (pointwise) map_finish(s, kFinishConfirm, v[1]);
+      else s.state = kConfirmPc;
+      break;
+    case kFinTail:
+      s.rs = v[0];
+      s.amax[1] = s.amax[2] = s.amax[3] = 0.0f;  // scaled-fp16 maxima of this application
+      map_finish(s, mode, v[0]);
+      break;
+    case kFinSum2:
+      s.rr = v[0];
+      s.bb = v[1];
+      break;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+static inline int egrid(const Engine& e, int ntiles) {
+  return std::max(1, std::min(ntiles, kEngineGrid));
+}
+
+EArgs make_args(const Engine& e) {
+  EArgs a;
+  a.desc = e.desc;
+  a.ms = e.ms;
+  a.tile_map = e.tile_map;
+  a.act = e.act;
+  a.counts = e.counts;
+  a.P = e.P;
+  a.pstride = e.pstride;
+  a.U = e.U;
+  a.V = e.V;
+  a.aux = e.aux;
+  a.x0 = e.x[0];
+  a.x1 = e.x[1];
+  a.d0 = e.d[0];
+  a.d1 = e.d[1];
+  a.r = e.r;
+  a.s = e.s;
+  a.q = e.q;
+  a.b = e.b;
+  a.dx = e.dx;
+  a.dy = e.dy;
+  a.phi_prev = e.phi_prev;
+  a.r64 = e.r64;
+  a.iso = e.iso;
+  return a;
+}
+
+void e_wrapdiff(hipStream_t st, const Engine& e, int ntiles) {
+  hipLaunchKernelGGL(k_e_wrapdiff, dim3(egrid(e, ntiles)), dim3(64), 0, st, make_args(e));
+}
+
+template <typename T>
+void e_weights(hipStream_t st, const Engine& e, int ntiles, double p, double tau) {
+  hipLaunchKernelGGL(k_e_weights<T>, dim3(egrid(e, ntiles)), dim3(64), 0, st, make_args(e),
+                     2.0 - p, tau);
+}
+
+template <typename T>
+void e_diag(hipStream_t st, const Engine& e, int ntiles, bool inv) {
+  hipLaunchKernelGGL(k_e_diag<T>, dim3(egrid(e, ntiles)), dim3(64), 0, st, make_args(e),
+                     inv ? 1 : 0);
+}
+
+template <typename T>
+void e_rhs(hipStream_t st, const Engine& e, int ntiles, int mode) {
+  hipLaunchKernelGGL(k_e_rhs<T>, dim3(egrid(e, ntiles)), dim3(64), 0, st, make_args(e), mode);
+}
+
+template <typename T>
+void e_pass(hipStream_t st, const Engine& e, int ntiles, int op) {
+  hipLaunchKernelGGL(k_e_pass<T>, dim3(egrid(e, ntiles)), dim3(64), 0, st, make_args(e), op);
+}
+
+template <typename T, int PC>
+static void e_resid_pc(hipStream_t st, const Engine& e, int ntiles, bool confirm) {
+  if (confirm)
+    hipLaunchKernelGGL((k_e_resid<T, PC, 1>), dim3(egrid(e, ntiles)), dim3(64), 0, st,
+                       make_args(e));
+  else
+    hipLaunchKernelGGL((k_e_resid<T, PC, 0>), dim3(egrid(e, ntiles)), dim3(64), 0, st,
+                       make_args(e));
+}
+
+template <typename T>
+void e_resid(hipStream_t st, const Engine& e, int ntiles, int pc, bool confirm) {
+  if (pc == kPcJacobi) e_resid_pc<T, kPcJacobi>(st, e, ntiles, confirm);
+  else e_resid_pc<T, kPcNone>(st, e, ntiles, confirm);
+}
+
+template <typename T>
+void e_spmv(hipStream_t st, const Engine& e, int ntiles, int pc) {
+  const int gr = egrid(e, ntiles);
+  if (pc == kPcNone)
+    hipLaunchKernelGGL((k_e_spmv<T, kPcNone>), dim3(gr), dim3(64), 0, st, make_args(e));
+  else if (pc == kPcJacobi)
+    hipLaunchKernelGGL((k_e_spmv<T, kPcJacobi>), dim3(gr), dim3(64), 0, st, make_args(e));
+  else
+    hipLaunchKernelGGL((k_e_spmv<T, kPcDct>), dim3(gr), dim3(64), 0, st, make_args(e));
+}
+
+template <typename T>
+void e_update(hipStream_t st, const Engine& e, int ntiles, int pc) {
+  const int gr = egrid(e, ntiles);
+  if (pc == kPcJacobi)
+    hipLaunchKernelGGL((k_e_update<T, kPcJacobi>), dim3(gr), dim3(64), 0, st, make_args(e));
+  else
+    hipLaunchKernelGGL((k_e_update<T, kPcNone>), dim3(gr), dim3(64), 0, st, make_args(e));
+}
+
+template <typename T>
+void e_apply(hipStream_t st, const Engine& e, int ntiles) {
+  hipLaunchKernelGGL(k_e_apply<T>, dim3(egrid(e, ntiles)), dim3(64), 0, st, make_args(e));
+}
+
+void e_finish(hipStream_t st, const Engine& e, int op, int expect, int mode, bool pointwise,
+              bool tail_single) {
+  hipLaunchKernelGGL(k_e_finish, dim3(e.n_maps), dim3(256), 0, st, e.desc, e.ms, e.P, e.pstride,
+                     op, expect, mode, pointwise ? 1 : 0, tail_single ? 1 : 0);
+}
+
+#define LPU_INST_E(T)                                                                   \
+  template void e_weights<T>(hipStream_t, const Engine&, int, double, double);         \
+  template void e_diag<T>(hipStream_t, const Engine&, int, bool);                      \
+  template void e_rhs<T>(hipStream_t, const Engine&, int, int);                        \
+  template void e_pass<T>(hipStream_t, const Engine&, int, int);                       \
+  template void e_resid<T>(hipStream_t, const Engine&, int, int, bool);                \
+  template void e_spmv<T>(hipStream_t, const Engine&, int, int);                       \
+  template void e_update<T>(hipStream_t, const Engine&, int, int);                     \
+  template void e_apply<T>(hipStream_t, const Engine&, int);
+LPU_INST_E(float)
+LPU_INST_E(double)
+
+}  // namespace lpu

@@ -1,0 +1,138 @@
+// Internal declarations shared by the HIP translation units of liblp_unwrap.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <deque>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/lp_unwrap.h"
+
+namespace lpu {
+
+constexpr double kPi = 3.141592653589793115997963468544185161590576171875;  // FP64 pi
+constexpr double kTwoPi = 2.0 * kPi;
+constexpr double kPivotFloor = 1e-4;  // ILU/IC pivot below this x diagonal -> diagonal
+
+// PCG state machine of one map, kept in device memory and advanced by the
+// finisher kernels, so the host can enqueue many iterations without reading
+// anything back.
+enum CgState : int {
+  kRun = 0,        // iterate
+  kConfirm = 1,    // the recursive residual met the bound: replace it by b - A x
+  kConfirmPc = 2,  // true residual formed, waiting for the preconditioner
+  kInitPc = 3,     // initial residual formed, waiting for the preconditioner
+  kDone = 4,       // stop rule met
+  kCap = 5,        // l_max reached
+  kBreakdown = 6   // d^T A d <= 0 or non-finite scalars
+};
+
+// How a finisher completes a PCG step.
+enum FinishMode : int { kFinishNone = 0, kFinishInit = 1, kFinishIter = 2, kFinishConfirm = 3 };
+
+enum PcKind : int { kPcNone = 0, kPcJacobi = 1, kPcIlu = 2, kPcIc = 3, kPcSsor = 4, kPcDct = 5 };
+
+// DCT tables for one size n, in every arithmetic the kernels use.
+struct DctTables {
+  int n = 0;
+  double* c64 = nullptr;    // C[k][j], n*n
+  double* ct64 = nullptr;   // C^T
+  float* c32 = nullptr;
+  float* ct32 = nullptr;
+  uint16_t* c_hi = nullptr;   // bf16 split of C
+  uint16_t* c_lo = nullptr;
+  uint16_t* ct_hi = nullptr;  // bf16 split of C^T
+  uint16_t* ct_lo = nullptr;
+  uint16_t* c_h = nullptr;    // fp16 C
+  uint16_t* ct_h = nullptr;   // fp16 C^T
+  double* lam = nullptr;      // 2 - 2 cos(pi k / n)
+};
+
+// HIP-event timing of selected kernel classes (instrumentation).
+struct KTimer {
+  unsigned int mask = 0;
+  struct Rec {
+    int a, b, cls;
+  };
+  std::vector<hipEvent_t> events;  // pool
+  std::vector<Rec> pending;
+  int next_event = 0;
+  double ms[LPU_KC_COUNT] = {};
+  long long n[LPU_KC_COUNT] = {};
+  double bytes[LPU_KC_COUNT] = {};
+  double flops[LPU_KC_COUNT] = {};
+  bool on(int cls) const { return (mask >> cls) & 1u; }
+  int begin(int cls, hipStream_t st);  // start event index or -1
+  void end(int idx, int cls, hipStream_t st);
+  // credit `launches` launches that did work, with their algorithmic figures
+  void credit(int cls, long long launches, double b, double f) {
+    if (!on(cls)) return;
+    n[cls] += launches;
+    bytes[cls] += b;
+    flops[cls] += f;
+  }
+  void flush();
+  void reset();
+  void destroy();
+};
+
+}  // namespace lpu
+
+#include "engine.h"
+
+struct lp_unwrap_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string last_error;
+  lpu::Engine eng;
+  std::deque<lpu::DctTables> dct;  // cached per size (deque: stable references)
+  std::vector<std::pair<int, lpu::DctTabDev*>> dct_dev;
+  hipEvent_t list_event = nullptr;  // last upload from the pinned list staging
+  bool list_event_live = false;
+  lpu::KTimer kt;
+};
+
+namespace lpu {
+
+int set_error(lp_unwrap_ctx* ctx, int code, const std::string& msg);
+#define LPU_HIP_CHECK(ctx, call)                                                       \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return ::lpu::set_error((ctx), LPU_ERR_HIP,                                      \
+                              std::string(#call) + ": " + hipGetErrorString(e_));      \
+  } while (0)
+
+const DctTables* get_dct_tables(lp_unwrap_ctx* ctx, int n, int* status);
+void free_dct_tables(lp_unwrap_ctx* ctx);
+
+// engine (driver.hip)
+int engine_solve(lp_unwrap_ctx* ctx, int n, const lpu_map* maps, double p, double tau, int pc,
+                 double tol, const lpu_options& o, lpu_stats* stats);
+void engine_release(lp_unwrap_ctx* ctx);
+int step_wrapdiff(lp_unwrap_ctx* ctx, int M, int N, const double* psi, double* dx, double* dy);
+template <typename T>
+int step_weights(lp_unwrap_ctx* ctx, int M, int N, const double* phi, const double* dx,
+                 const double* dy, const float* mask, double p, double tau, T* U, T* V);
+template <typename T>
+int step_apply(lp_unwrap_ctx* ctx, int M, int N, const T* U, const T* V, const T* x, T* y);
+template <typename T>
+int step_rhs(lp_unwrap_ctx* ctx, int M, int N, const T* U, const T* V, const double* dx,
+             const double* dy, double* b);
+template <typename T>
+int step_pivots(lp_unwrap_ctx* ctx, int M, int N, const T* U, const T* V, T* piv, bool ssor,
+                double omega);
+template <typename T>
+int step_precond(lp_unwrap_ctx* ctx, int M, int N, int pc, int dct_mode, double omega, const T* U,
+                 const T* V, const T* r, T* s);
+
+// small utilities (util.hip)
+void launch_finite_check(hipStream_t st, size_t n, const double* psi, const float* mask,
+                         unsigned int* bad);
+template <typename T>
+void launch_scale_by(hipStream_t st, size_t n, const T* a, const T* b, T* out);
+
+}  // namespace lpu

@@ -1,0 +1,354 @@
+"""Solver parity: the whole HIP path (Algorithm 1) against the oracle.
+
+* FP64 path vs the oracle running the same algorithm (same preconditioner,
+  stop rule, replacement period, start value and outer count): the inner
+  iteration counts agree up to rounding-induced +-1 per solve, and the unwrapped
+  phases agree (mean removed) to the accuracy two solves at relres 1e-6 can
+  share.
+* Mixed path vs the oracle with exact inner solves (relres 1e-12): reported
+  per case and bounded.
+* Edge cases: 1x1, one-row and one-column maps, all-zero mask, NaN input,
+  invalid arguments, iteration caps.
+"""
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from paper_2203_13675_amd import synth  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2203_13675_amd.binding import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def dev(a, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda", dtype)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.double().cpu().numpy()
+
+
+def demean(a, valid=None):
+    if valid is None:
+        return a - a.mean()
+    out = a.copy()
+    out[valid] -= a[valid].mean()
+    out[~valid] = 0.0
+    return out
+
+
+def maxdiff(a, b, valid=None):
+    return float(np.abs(demean(a, valid) - demean(b, valid)).max())
+
+
+# ---------------------------------------------------------------------------
+# FP64 path vs the oracle's same algorithm
+# ---------------------------------------------------------------------------
+def oracle_sensitivity(oracle, psi, mask, valid=None, samples=3, **kw):
+    """How far the oracle's own answer moves when psi is perturbed at the level
+    of accumulated rounding (1e-14 relative), maximised over a few seeds: the
+    accuracy two correct implementations of the same algorithm can share."""
+    a = oracle.unwrap(psi, mask, **kw)
+    worst = 0.0
+    for seed in range(samples):
+        rng = np.random.default_rng(123 + seed)
+        b = oracle.unwrap(psi * (1 + 1e-14 * rng.standard_normal(psi.shape)), mask, **kw)
+        worst = max(worst, maxdiff(a.phi, b.phi, valid))
+    return a, worst
+
+
+FIXED_CASES = [("peaks64", None), ("ragged", None), ("hole", "hole")]
+
+
+def _case(name):
+    if name == "peaks64":
+        psi, _, _ = synth.workload("peaks64")
+        return psi, None
+    if name == "ragged":
+        psi, _ = synth.peaks_map(37, 53, scale=2.0, sigma=0.2, seed=90)
+        return psi, None
+    psi, _ = synth.gaussians_map(96, 80, width=(10, 40), sigma=0.3, seed=9)
+    return psi, synth.hole_mask(96, 80, 0.10, seed=10)
+
+
+@pytest.mark.parametrize("pc", ["none", "jacobi", "ilu0", "ic0", "ssor", "dct"])
+@pytest.mark.parametrize("case", ["peaks64", "ragged", "hole"])
+@pytest.mark.parametrize("k_max", [1, 3])
+def test_fp64_fixed_work_matches_oracle(ctx, oracle, pc, case, k_max):
+    """Same algorithm, same work: the stop rule is disabled (tol = 0) and every
+    inner solve runs exactly 25 PCG iterations (well before convergence), from
+    the same random start.  Differences are rounding only."""
+    psi, mask = _case(case)
+    M, N = psi.shape
+    valid = None if mask is None else mask > 0
+    phi0 = synth.random_phi0(M, N, seed=3)
+    kw = dict(p=0.0, precond=pc, k_max=k_max, outer_tol=0.0, tol=0.0, l_max=25, phi0=phi0)
+    ref, sens = oracle_sensitivity(oracle, psi, mask, valid, **kw)
+    res = ctx.solve(dev(psi), None if mask is None else dev(mask, torch.float32), p=0.0,
+                    preconditioner=pc, tol=0.0, precision="fp64", k_max=k_max, outer_tol=0.0,
+                    l_max=25, phi=dev(phi0), use_phi0=1, check=False)
+    phi = host(res.phi)
+    scale = np.abs(ref.phi).max()
+    d = maxdiff(phi, ref.phi, valid)
+    print("fixed-work", case, pc, k_max, "maxdiff", d, "oracle sensitivity", sens)
+    assert res.stats["inner_iters_total"] == 25 * k_max
+    assert d <= max(1e-10 * scale, 50 * sens)
+    if valid is not None:
+        assert np.array_equal(phi[~valid], phi0[~valid])
+
+
+@pytest.mark.parametrize("pc", ["none", "jacobi", "ilu0", "ic0", "ssor", "dct"])
+def test_fp64_peaks64_matches_oracle(ctx, oracle, pc):
+    """64x64 peaks map, p = 0, tau = 0.01, 10 outer iterations, inner relres
+    1e-6 (the small plain-FP64 workload).  Bounded by the oracle's own
+    sensitivity to a rounding-level perturbation of the input."""
+    psi, _, _ = synth.workload("peaks64")
+    ref, sens = oracle_sensitivity(oracle, psi, None, p=0.0, precond=pc, k_max=10, outer_tol=0.0)
+    res = ctx.solve(dev(psi), p=0.0, eps=0.01, preconditioner=pc, tol=1e-6, precision="fp64",
+                    k_max=10, outer_tol=0.0)
+    phi = host(res.phi)
+    it_ref = sum(ref.inner_iters)
+    it = res.stats["inner_iters_total"]
+    d = maxdiff(phi, ref.phi)
+    print(pc, "iters gpu", it, "oracle", it_ref, "maxdiff", d, "sensitivity", sens)
+    assert abs(it - it_ref) <= 10 + 0.03 * it_ref
+    assert d <= max(1e-6, 50 * sens)
+    assert res.stats["final_relres"] <= 1e-6
+
+
+@pytest.mark.parametrize("M,N", [(37, 53), (1, 60), (60, 1), (130, 77)])
+@pytest.mark.parametrize("pc", ["jacobi", "ilu0", "dct"])
+def test_fp64_ragged_matches_oracle(ctx, oracle, M, N, pc):
+    psi, _ = synth.peaks_map(M, N, scale=2.0, sigma=0.2, seed=M + N)
+    ref, sens = oracle_sensitivity(oracle, psi, None, p=1.0, precond=pc, k_max=4, outer_tol=0.0)
+    res = ctx.solve(dev(psi), p=1.0, preconditioner=pc, tol=1e-6, precision="fp64", k_max=4,
+                    outer_tol=0.0)
+    d = maxdiff(host(res.phi), ref.phi)
+    print("ragged", M, N, pc, "maxdiff", d, "sensitivity", sens)
+    assert d <= max(1e-6, 50 * sens)
+    assert res.stats["final_relres"] <= 1e-6
+
+
+def test_fp64_paper_stop_rule_and_random_start(ctx, oracle):
+    """Algorithm 1 as printed: random start, eps = 0.005 on the preconditioned
+    residual, outer test on the relative change."""
+    M, N = 48, 40
+    psi, _ = synth.peaks_map(M, N, scale=3.0, sigma=0.3, seed=5)
+    phi0 = synth.random_phi0(M, N, seed=6)
+    ref, sens = oracle_sensitivity(oracle, psi, None, p=0.0, precond="ilu0", stop_rule="paper",
+                                   k_max=6, outer_tol=0.0, phi0=phi0)
+    res = ctx.solve(dev(psi), p=0.0, preconditioner="ilu0", precision="fp64", stop_rule="paper",
+                    k_max=6, outer_tol=0.0, phi=dev(phi0), use_phi0=1)
+    d = maxdiff(host(res.phi), ref.phi)
+    print("paper rule: iters", res.stats["inner_iters_total"], sum(ref.inner_iters), "maxdiff", d,
+          "sensitivity", sens)
+    assert abs(res.stats["inner_iters_total"] - sum(ref.inner_iters)) <= 6
+    assert d <= max(1e-6, 50 * sens)
+
+
+def test_fp64_hole_mask(ctx, oracle):
+    M, N = 96, 80
+    psi, _ = synth.gaussians_map(M, N, width=(10, 40), sigma=0.3, seed=9)
+    mask = synth.hole_mask(M, N, 0.10, seed=10)
+    valid = mask > 0
+    for pc in ("jacobi", "ilu0", "dct"):
+        ref, sens = oracle_sensitivity(oracle, psi, mask, valid, p=0.0, precond=pc, k_max=5,
+                                       outer_tol=0.0)
+        res = ctx.solve(dev(psi), dev(mask, torch.float32), p=0.0, preconditioner=pc,
+                        precision="fp64", k_max=5, outer_tol=0.0)
+        phi = host(res.phi)
+        d = maxdiff(phi, ref.phi, valid)
+        print("hole", pc, "maxdiff", d, "sensitivity", sens)
+        assert d <= max(1e-6, 50 * sens), pc
+        assert np.all(phi[~valid] == 0.0)
+
+
+# ---------------------------------------------------------------------------
+# Mixed path vs exact inner solves
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("pc,mode", [("dct", "split_bf16"), ("dct", "fp16_scaled"), ("dct", "fp32"),
+                                     ("jacobi", "split_bf16"), ("ilu0", "split_bf16"),
+                                     ("none", "split_bf16"), ("ssor", "split_bf16")])
+def test_mixed_peaks64_vs_exact(ctx, oracle, pc, mode):
+    """Mixed precision at relres 1e-6 against exact inner solves: the error is
+    bounded by what the FP64 oracle itself commits at the same tolerance (the
+    stopping rule, not the arithmetic, sets the accuracy)."""
+    psi, _, _ = synth.workload("peaks64")
+    ex = oracle.unwrap_exact(psi, p=0.0, outer=10)
+    same_tol = oracle.unwrap(psi, p=0.0, precond=pc, tol=1e-6, k_max=10, outer_tol=0.0)
+    res = ctx.solve(dev(psi), p=0.0, preconditioner=pc, tol=1e-6, precision="mixed",
+                    dct_mode=mode, k_max=10, outer_tol=0.0)
+    phi = host(res.phi)
+    d = maxdiff(phi, ex.phi)
+    d_orc = maxdiff(same_tol.phi, ex.phi)
+    print(pc, mode, "maxdiff vs exact", d, "oracle at 1e-6 vs exact", d_orc, res.stats)
+    assert res.stats["final_relres"] <= 1e-6
+    assert d <= max(3.0 * d_orc, 1e-5)
+
+
+def test_mixed_matches_fp64_same_preconditioner(ctx):
+    """Mixed and FP64 GPU solves of the same problem agree to the accuracy of
+    relres 1e-6 solves (no outer-iteration divergence on this map)."""
+    psi, _ = synth.peaks_map(128, 96, scale=3.0, sigma=0.3, seed=21)
+    a = ctx.solve(dev(psi), p=0.0, preconditioner="dct", precision="fp64", k_max=10, outer_tol=0.0)
+    b = ctx.solve(dev(psi), p=0.0, preconditioner="dct", precision="mixed", k_max=10, outer_tol=0.0)
+    assert maxdiff(host(a.phi), host(b.phi)) <= 1e-3
+
+
+# ---------------------------------------------------------------------------
+# Closed-form special cases on the GPU
+# ---------------------------------------------------------------------------
+def test_exact_recovery(ctx):
+    """Noise-free phase with neighbour differences below pi is recovered up to
+    a constant by one outer step, for every p and preconditioner."""
+    M, N = 80, 96
+    phi = synth.peaks(M, N) * 0.8 + np.linspace(0, 6, N)[None, :]
+    psi = synth.wrap_measurement(phi)
+    for p in (0.0, 1.0, 2.0):
+        for pc in ("jacobi", "ilu0", "dct"):
+            for prec in ("fp64", "mixed"):
+                res = ctx.solve(dev(psi), p=p, preconditioner=pc, tol=1e-10 if prec == "fp64" else 1e-7,
+                                precision=prec, k_max=1, outer_tol=0.0)
+                e = host(res.phi) - phi
+                assert np.ptp(e) < (1e-6 if prec == "fp64" else 1e-4), (p, pc, prec, np.ptp(e))
+
+
+def test_p2_dct_one_iteration(ctx):
+    """p = 2: constant weights, the DCT preconditioner is exact: one PCG step."""
+    psi, _ = synth.peaks_map(64, 48, scale=4.0, sigma=0.3, seed=3)
+    res = ctx.solve(dev(psi), p=2.0, preconditioner="dct", tol=1e-10, precision="fp64", k_max=1,
+                    outer_tol=0.0)
+    assert res.stats["inner_iters_total"] == 1
+    assert res.stats["final_relres"] < 1e-11
+
+
+# ---------------------------------------------------------------------------
+# Edge cases and errors
+# ---------------------------------------------------------------------------
+def test_one_pixel_map(ctx):
+    psi = np.array([[0.3]])
+    res = ctx.solve(dev(psi), precision="fp64", k_max=3, outer_tol=0.0)
+    assert res.status == 0 and host(res.phi)[0, 0] == 0.0
+
+
+@pytest.mark.parametrize("shape", [(1, 200), (200, 1)])
+@pytest.mark.parametrize("pc", ["none", "jacobi", "ilu0", "ic0", "ssor", "dct"])
+def test_one_dimensional_maps(ctx, oracle, shape, pc):
+    rng = np.random.default_rng(4)
+    phi_true = np.cumsum(rng.normal(0, 0.6, shape[0] * shape[1])).reshape(shape)
+    psi = synth.wrap_measurement(phi_true)
+    ref, sens = oracle_sensitivity(oracle, psi, None, p=0.0, precond=pc, k_max=3, outer_tol=0.0)
+    res = ctx.solve(dev(psi), p=0.0, preconditioner=pc, precision="fp64", k_max=3, outer_tol=0.0)
+    d = maxdiff(host(res.phi), ref.phi)
+    print("1-D", shape, pc, "maxdiff", d, "sensitivity", sens)
+    assert d <= max(1e-6, 50 * sens)
+
+
+def test_all_zero_mask_keeps_phi0(ctx):
+    M, N = 20, 30
+    psi = np.random.default_rng(0).uniform(-3, 3, (M, N))
+    phi0 = np.random.default_rng(1).normal(size=(M, N))
+    mask = np.zeros((M, N), dtype=np.float32)
+    for pc in ("jacobi", "ilu0", "dct"):
+        res = ctx.solve(dev(psi), dev(mask, torch.float32), preconditioner=pc, precision="fp64",
+                        phi=dev(phi0), use_phi0=1, k_max=2, outer_tol=0.0)
+        assert res.status == 0
+        assert np.array_equal(host(res.phi), phi0)
+
+
+def test_nonfinite_input(ctx):
+    from paper_2203_13675_amd import binding
+    psi = np.zeros((16, 16))
+    psi[3, 4] = np.nan
+    res = ctx.solve(dev(psi), check=False)
+    assert res.status == binding.ERR_NONFINITE
+    mask = np.ones((16, 16), dtype=np.float32)
+    mask[0, 0] = np.inf
+    res = ctx.solve(dev(np.zeros((16, 16))), dev(mask, torch.float32), check=False)
+    assert res.status == binding.ERR_NONFINITE
+
+
+def test_invalid_arguments(ctx):
+    from paper_2203_13675_amd import binding
+    psi = dev(np.zeros((8, 8)))
+    for kw in (dict(p=3.0), dict(p=-0.5), dict(eps=0.0), dict(tol=-1.0), dict(preconditioner=9),
+               dict(ssor_omega=2.0), dict(k_max=-1), dict(refine_eta=1.5)):
+        res = ctx.solve(psi, check=False, **kw)
+        assert res.status == binding.ERR_INVALID_ARG, kw
+    lib = binding.lib()
+    st = binding.LpuStats()
+    assert lib.lp_unwrap_solve(ctx._h, 0, 8, psi.data_ptr(), None, 0.0, 0.01, 5, 1e-6, None,
+                               psi.data_ptr(), st) == binding.ERR_INVALID_ARG
+    assert lib.lp_unwrap_solve(ctx._h, 8, 8, None, None, 0.0, 0.01, 5, 1e-6, None,
+                               psi.data_ptr(), st) == binding.ERR_INVALID_ARG
+    assert len(ctx.last_error()) > 0
+
+
+def test_iteration_caps(ctx):
+    from paper_2203_13675_amd import binding
+    psi, _, _ = synth.workload("peaks64")
+    res = ctx.solve(dev(psi), precision="fp64", l_max=1, k_max=2, outer_tol=0.0, check=False)
+    assert res.status == binding.NOT_CONVERGED
+    assert res.stats["inner_iters_total"] == 2
+    res = ctx.solve(dev(psi), precision="fp64", k_max=1, outer_tol=1e-12, check=False)
+    assert res.status == binding.NOT_CONVERGED and res.stats["outer_iters"] == 1
+
+
+def test_outer_convergence_stops_early(ctx, oracle):
+    """With the paper's outer test (tol 1e-6 on the relative change) the loop
+    stops at the fixed point, as the oracle does."""
+    psi, _, _ = synth.workload("peaks64")
+    ref = oracle.unwrap(psi, p=0.0, precond="dct", k_max=50, outer_tol=1e-6)
+    res = ctx.solve(dev(psi), p=0.0, preconditioner="dct", precision="fp64", k_max=50,
+                    outer_tol=1e-6)
+    assert res.status == 0
+    assert abs(res.stats["outer_iters"] - ref.outer_iters) <= 1
+
+
+def test_resume_from_saved_phi(ctx):
+    """Checkpoint/resume: k outer steps then k more from the saved phi equal
+    2k steps in one call (same kernels, same order)."""
+    psi, _, _ = synth.workload("peaks64")
+    full = ctx.solve(dev(psi), precision="fp64", preconditioner="jacobi", k_max=6, outer_tol=0.0)
+    half = ctx.solve(dev(psi), precision="fp64", preconditioner="jacobi", k_max=3, outer_tol=0.0)
+    rest = ctx.solve(dev(psi), precision="fp64", preconditioner="jacobi", k_max=3, outer_tol=0.0,
+                     phi=half.phi.clone(), use_phi0=1)
+    assert np.array_equal(host(full.phi), host(rest.phi))
+
+
+def test_deterministic(ctx):
+    """Two identical runs give bit-identical results (fixed-order reductions)."""
+    psi, _ = synth.peaks_map(200, 160, scale=6.0, sigma=0.4, seed=2)
+    a = ctx.solve(dev(psi), precision="mixed", preconditioner="dct", k_max=3, outer_tol=0.0)
+    b = ctx.solve(dev(psi), precision="mixed", preconditioner="dct", k_max=3, outer_tol=0.0)
+    assert np.array_equal(host(a.phi), host(b.phi))
+
+
+# ---------------------------------------------------------------------------
+# Batch
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("pc", ["jacobi", "dct"])
+def test_batch_matches_single(ctx, pc):
+    shapes = [(64, 64), (37, 53), (128, 96), (16, 200)]
+    maps = synth.batch_maps(sides=shapes, seed=77)
+    psis = [dev(p) for p, _ in maps]
+    phis, rc, stats = ctx.batch(psis, p=0.0, preconditioner=pc, precision="mixed", k_max=4,
+                                outer_tol=0.0)
+    for k, (p, _) in enumerate(maps):
+        single = ctx.solve(dev(p), p=0.0, preconditioner=pc, precision="mixed", k_max=4,
+                           outer_tol=0.0)
+        assert maxdiff(host(phis[k]), host(single.phi)) <= 1e-4
+        assert stats[k]["final_relres"] <= 1e-6
