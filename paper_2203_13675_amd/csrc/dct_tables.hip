@@ -30,7 +30,8 @@ static float bf16_to_f32(uint16_t h) {
 }
 
 static void free_tables(DctTables& t) {
-  void* tp[] = {t.c64, t.ct64, t.c32, t.ct32, t.c_hi, t.c_lo, t.ct_hi, t.ct_lo, t.c_h, t.ct_h, t.lam};
+  void* tp[] = {t.c64,   t.ct64,   t.c32,  t.ct32,   t.c_hi,   t.c_lo, t.ct_hi,    t.ct_lo, t.c_h,
+                t.ct_h,  t.lam,    t.eo_hi, t.eo_lo, t.eo_h, t.eot_hi, t.eot_lo, t.eot_h, t.lam_split};
   for (void* p : tp)
     if (p) (void)hipFree(p);
 }
@@ -86,6 +87,39 @@ const DctTables* get_dct_tables(lp_unwrap_ctx* ctx, int n, int* status) {
   up((void**)&t.c_h, ch.data(), nn * 2);
   up((void**)&t.ct_h, cth.data(), nn * 2);
   up((void**)&t.lam, lam.data(), (size_t)n * 8);
+  if (n % 128 == 0) {
+    // even/odd split: C[k][n-1-j] = (-1)^k C[k][j]
+    const int h = n / 2;
+    const size_t nh = (size_t)n * h;
+    std::vector<uint16_t> eh(nh), el(nh), e16(nh), th(nh), tl(nh), t16(nh);
+    std::vector<double> ls(n);
+    for (int c = 0; c < n; ++c) {
+      const int k = c < h ? 2 * c : 2 * (c - h) + 1;
+      ls[c] = lam[k];
+      for (int j = 0; j < h; ++j) {
+        const float v = c32[(size_t)k * n + j];
+        const uint16_t hi = f32_to_bf16_rne(v);
+        const uint16_t lo = f32_to_bf16_rne(v - bf16_to_f32(hi));
+        const _Float16 hv = (_Float16)v;
+        uint16_t hb;
+        std::memcpy(&hb, &hv, 2);
+        // EO[c][j] and EOt[j][c]
+        eh[(size_t)c * h + j] = hi;
+        el[(size_t)c * h + j] = lo;
+        e16[(size_t)c * h + j] = hb;
+        th[(size_t)j * n + c] = hi;
+        tl[(size_t)j * n + c] = lo;
+        t16[(size_t)j * n + c] = hb;
+      }
+    }
+    up((void**)&t.eo_hi, eh.data(), nh * 2);
+    up((void**)&t.eo_lo, el.data(), nh * 2);
+    up((void**)&t.eo_h, e16.data(), nh * 2);
+    up((void**)&t.eot_hi, th.data(), nh * 2);
+    up((void**)&t.eot_lo, tl.data(), nh * 2);
+    up((void**)&t.eot_h, t16.data(), nh * 2);
+    up((void**)&t.lam_split, ls.data(), (size_t)n * 8);
+  }
   if (!ok) {
     free_tables(t);
     *status = set_error(ctx, LPU_ERR_OOM, "DCT table allocation failed");

@@ -44,6 +44,18 @@ enum FinOpH { kFinInitH = 0, kFinAlphaH = 1, kFinUpdateH = 2, kFinConfirmH = 3, 
 enum PassOp { kPassSavePhi = 0, kPassX0Phi = 1, kPassX0Zero = 2, kPassPhiAdd = 3,
               kPassDiffNorms = 4, kPassPhiSet = 5 };
 
+// Contraction kernel of the DCT stages: 0 FP64 FMA, 1 FP32 FMA, 2 split-bf16
+// MFMA, 3 scaled-fp16 MFMA, 4/5 the even/odd MFMA versions of 2/3 (every map
+// side a multiple of 128).
+static int dct_kind_for(const Engine& e, bool mixed, int dct_mode) {
+  if (!mixed) return 0;
+  if (dct_mode == LPU_DCT_FP32) return 1;
+  bool sym = true;
+  for (const MapDesc& d : e.hdesc) sym = sym && (d.M % 128 == 0) && (d.N % 128 == 0);
+  const int k = dct_mode == LPU_DCT_SPLIT_BF16 ? 2 : 3;
+  return sym ? k + 2 : k;
+}
+
 static double now_ms() {
   using namespace std::chrono;
   return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
@@ -85,6 +97,13 @@ static const DctTabDev* dct_dev(lp_unwrap_ctx* ctx, int n, int* status) {
   h.ch = t->c_h;
   h.cth = t->ct_h;
   h.lam = t->lam;
+  h.eo_hi = t->eo_hi;
+  h.eo_lo = t->eo_lo;
+  h.eo_h = t->eo_h;
+  h.eot_hi = t->eot_hi;
+  h.eot_lo = t->eot_lo;
+  h.eot_h = t->eot_h;
+  h.lam_split = t->lam_split;
   DctTabDev* d = nullptr;
   if (hipMalloc((void**)&d, sizeof(DctTabDev)) != hipSuccess ||
       hipMemcpy(d, &h, sizeof(DctTabDev), hipMemcpyHostToDevice) != hipSuccess) {
@@ -416,8 +435,7 @@ static int run_maps(lp_unwrap_ctx* ctx, int n, const lpu_map* maps, double p, do
   std::vector<double> err(n, INFINITY), relres(n, 0.0);
   std::vector<bool> finished(n, false), outer_conv(n, false), inner_ok(n, true);
   double setup_ms = 0.0;
-  Pcg<T> pcg{ctx, pc, mixed ? (o.dct_mode == LPU_DCT_FP32 ? 1 : (o.dct_mode == LPU_DCT_SPLIT_BF16 ? 2 : 3)) : 0,
-             o.ssor_omega};
+  Pcg<T> pcg{ctx, pc, dct_kind_for(e, mixed, o.dct_mode), o.ssor_omega};
 
   auto credit = [&](const std::vector<int>& set) {
     // algorithmic figures of the PCG launches that did work
@@ -429,10 +447,16 @@ static int run_maps(lp_unwrap_ctx* ctx, int n, const lpu_map* maps, double p, do
       kt.credit(LPU_KC_UPDATE, s.l, s.l * px * el * (6.0 + jac), s.l * px * 8.0);
       const double Mm = maps[m].rows, Nn = maps[m].cols;
       if (pc == kPcDct) {
-        const double prod = pcg.dct_kind == 2 ? 3.0 : 1.0;
-        const double tab = pcg.dct_kind == 0 ? 8.0 : (pcg.dct_kind == 1 ? 4.0 : (pcg.dct_kind == 2 ? 4.0 : 2.0));
-        const double bytes = 2.0 * (2.0 * px * el + Nn * Nn * tab) + 2.0 * (2.0 * px * el + Mm * Mm * tab) + px * el;
-        kt.credit(LPU_KC_DCT, 4 * s.nfinish, s.nfinish * bytes, s.nfinish * 4.0 * px * (Mm + Nn) * prod);
+        // per application: 4 contractions; MFMA products per multiply-add
+        // (3 for the bf16 split); the even/odd kernels do half the work
+        const int kd = pcg.dct_kind;
+        const double prod = (kd == 2 || kd == 4) ? 3.0 : 1.0;
+        const double half = kd >= 4 ? 0.5 : 1.0;
+        const double tab = kd == 0 ? 8.0 : (kd == 1 ? 4.0 : ((kd == 2 || kd == 4) ? 4.0 : 2.0));
+        const double bytes = 2.0 * (2.0 * px * el + half * Nn * Nn * tab) +
+                             2.0 * (2.0 * px * el + half * Mm * Mm * tab) + px * el;
+        kt.credit(LPU_KC_DCT, 4 * s.nfinish, s.nfinish * bytes,
+                  s.nfinish * 4.0 * px * (Mm + Nn) * prod * half);
       } else if (!pcg.pointwise()) {
         kt.credit(LPU_KC_SWEEP, s.nfinish, s.nfinish * px * el * 10.0, s.nfinish * px * 14.0);
       }
@@ -706,7 +730,7 @@ int step_precond(lp_unwrap_ctx* ctx, int M, int N, int pc, int dct_mode, double 
   } else if (pc == kPcJacobi) {
     launch_scale_by<T>(st, n, r, (const T*)e.aux, s);
   } else if (pc == kPcDct) {
-    const int kind = sizeof(T) == 8 ? 0 : (dct_mode == LPU_DCT_FP32 ? 1 : (dct_mode == LPU_DCT_SPLIT_BF16 ? 2 : 3));
+    const int kind = dct_kind_for(e, sizeof(T) == 4, dct_mode);
     const void* in[4] = {e.r, e.t1, e.t2, e.t1};
     void* out[4] = {e.t1, e.t2, e.t1, e.s};
     for (int k = 0; k < 4; ++k) e_dct_stage(st, e, e.total_dtiles, k, kRun, kind, in[k], out[k], e.r);

@@ -40,6 +40,13 @@ struct DctTabDev {
   const uint16_t* ch;
   const uint16_t* cth;
   const double* lam;
+  const uint16_t* eo_hi;   // even/odd split tables (null unless n % 128 == 0)
+  const uint16_t* eo_lo;
+  const uint16_t* eo_h;
+  const uint16_t* eot_hi;
+  const uint16_t* eot_lo;
+  const uint16_t* eot_h;
+  const double* lam_split;
 };
 
 struct MapDesc {

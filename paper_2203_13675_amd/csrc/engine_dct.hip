@@ -229,6 +229,200 @@ __global__ void __launch_bounds__(256) k_e_dct_mfma(DArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Even/odd MFMA stage (mixed path, both sides multiples of 128).
+//
+// The basis satisfies C[k][n-1-j] = (-1)^k C[k][j].  With h = n/2 and the
+// spectrum kept in split order (even k first):
+//   forward  X_even = E (x_a + x_b),  X_odd = O (x_a - x_b),
+//            x_a = x[0..h), x_b = x[n-1 .. h] (mirrored), E, O the h x h
+//            even/odd rows of C restricted to j < h;
+//   inverse  u = E^T X_even, v = O^T X_odd;  x[j] = u_j + v_j,
+//            x[n-1-j] = u_j - v_j  (j < h).
+// Both halve the multiply-adds of the dense transform.  A block owns a
+// 64 x 64 output tile (inverse: columns c < h, writing c and n-1-c); X
+// (converted once to bf16 hi/lo or scaled fp16) and the table slice are
+// staged in double-buffered LDS, the next K step is fetched into registers
+// while the MFMAs of the current one run.
+// ---------------------------------------------------------------------------
+constexpr int kLp = 40;  // LDS row pitch in 16-bit elements (32 + 8 padding)
+
+template <int SPLIT>
+__global__ void __launch_bounds__(256) k_e_dct_sym(DArgs a) {
+  __shared__ __attribute__((aligned(16))) uint16_t Xh[2][64][kLp];
+  __shared__ __attribute__((aligned(16))) uint16_t Xl[2][64][kLp];
+  __shared__ __attribute__((aligned(16))) uint16_t Bh[2][64][kLp];
+  __shared__ __attribute__((aligned(16))) uint16_t Bl[2][64][kLp];
+  __shared__ double red[4];
+  const int nact = a.counts[1];
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int lrow = tid >> 2, lk = (tid & 3) * 8;          // staging assignment
+  const int wr = (w & 1) * 32, wc = (w >> 1) * 32;         // wave sub-tile
+  const int lr = lane & 15, kg = (lane >> 4) * 8;          // MFMA operand lane map
+  const bool inverse = a.stage >= 2;
+  for (int t_ = blockIdx.x; t_ < nact; t_ += gridDim.x) {
+    const int g = a.dact[t_];
+    const DTile t = dtile(a, g);
+    if (!t.ok) continue;  // uniform over the block
+    const int R = t.R, n = t.K, h = n >> 1;
+    if (inverse && t.c0 >= h) {
+      if (a.stage == 3 && tid == 0) a.P[1 * a.pstride + g] = 0.0;
+      continue;
+    }
+    const float* X = reinterpret_cast<const float*>(a.X) + t.off;
+    float* Out = reinterpret_cast<float*>(a.Out) + t.off;
+    const uint16_t* Th = inverse ? (SPLIT ? t.tab->eot_hi : t.tab->eot_h) : (SPLIT ? t.tab->eo_hi : t.tab->eo_h);
+    const uint16_t* Tl = inverse ? t.tab->eot_lo : t.tab->eo_lo;
+    const int tpitch = inverse ? n : h;
+    const float sign = (!inverse && t.c0 >= h) ? -1.0f : 1.0f;
+    const int keff = inverse ? n : h;
+    const int nsteps = keff / 32;
+    MapState& st = a.ms[t.m];
+    float xs = 1.0f, inv_xs = 1.0f;
+    if (!SPLIT) {
+      float amax = a.stage == 0 ? (float)sqrt(st.rr) * 1.0000001f : st.amax[a.stage];
+      if (!inverse) amax *= 2.0f;  // x_a +- x_b
+      xs = fp16_scale(amax);
+      inv_xs = 1.0f / xs;
+    }
+    const float* xrow = X + (size_t)(t.r0 + lrow) * n;
+    const uint16_t* trow_h = Th + (size_t)(t.c0 + lrow) * tpitch;
+    const uint16_t* trow_l = Tl + (size_t)(t.c0 + lrow) * tpitch;
+    // register staging of one K step
+    u16x8 sxh, sxl, sbh, sbl;
+    auto fetch = [&](int k0) {
+      const int k = k0 + lk;
+      const float4* pa = reinterpret_cast<const float4*>(xrow + k);
+      const float4 a0 = pa[0], a1 = pa[1];
+      float v[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+      if (!inverse) {
+        const float4* pb = reinterpret_cast<const float4*>(xrow + (n - 8 - k));
+        const float4 b0 = pb[0], b1 = pb[1];
+        const float m[8] = {b1.w, b1.z, b1.y, b1.x, b0.w, b0.z, b0.y, b0.x};
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] += sign * m[e];
+      }
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        if (SPLIT) {
+          const __bf16 hb = (__bf16)v[e];
+          sxh[e] = __builtin_bit_cast(uint16_t, hb);
+          sxl[e] = __builtin_bit_cast(uint16_t, (__bf16)(v[e] - (float)hb));
+        } else {
+          sxh[e] = __builtin_bit_cast(uint16_t, (_Float16)(v[e] * xs));
+        }
+      }
+      sbh = *reinterpret_cast<const u16x8*>(trow_h + k);
+      if (SPLIT) sbl = *reinterpret_cast<const u16x8*>(trow_l + k);
+    };
+    auto stash = [&](int buf) {
+      *reinterpret_cast<u16x8*>(&Xh[buf][lrow][lk]) = sxh;
+      *reinterpret_cast<u16x8*>(&Bh[buf][lrow][lk]) = sbh;
+      if (SPLIT) {
+        *reinterpret_cast<u16x8*>(&Xl[buf][lrow][lk]) = sxl;
+        *reinterpret_cast<u16x8*>(&Bl[buf][lrow][lk]) = sbl;
+      }
+    };
+    f32x4 U[2][2], V[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) U[i][j] = V[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    __syncthreads();  // previous tile's readers are done with the buffers
+    fetch(0);
+    stash(0);
+    __syncthreads();
+    for (int s = 0; s < nsteps; ++s) {
+      const int buf = s & 1;
+      if (s + 1 < nsteps) fetch((s + 1) * 32);
+      const bool second = inverse && (s * 32 >= h);  // accumulate v after the even half
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const u16x8 ah = *reinterpret_cast<const u16x8*>(&Xh[buf][wr + i * 16 + lr][kg]);
+        u16x8 al;
+        if (SPLIT) al = *reinterpret_cast<const u16x8*>(&Xl[buf][wr + i * 16 + lr][kg]);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const u16x8 bh = *reinterpret_cast<const u16x8*>(&Bh[buf][wc + j * 16 + lr][kg]);
+          f32x4 acc = second ? V[i][j] : U[i][j];
+          if (SPLIT) {
+            const u16x8 bl = *reinterpret_cast<const u16x8*>(&Bl[buf][wc + j * 16 + lr][kg]);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, ah),
+                                                         __builtin_bit_cast(bf16x8, bh), acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, ah),
+                                                         __builtin_bit_cast(bf16x8, bl), acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, al),
+                                                         __builtin_bit_cast(bf16x8, bh), acc, 0, 0, 0);
+          } else {
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, ah),
+                                                        __builtin_bit_cast(f16x8, bh), acc, 0, 0, 0);
+          }
+          if (second) V[i][j] = acc;
+          else U[i][j] = acc;
+        }
+      }
+      if (s + 1 < nsteps) stash(buf ^ 1);
+      __syncthreads();
+    }
+    // epilogue: lane holds D[row 4*(lane/16) + e][col lane mod 16] of each 16x16 tile
+    const MapDesc& d = a.desc[t.m];
+    const float* rv = reinterpret_cast<const float*>(a.rvec) + t.off;
+    const unsigned char* iso = (a.iso && d.use_iso) ? a.iso + t.off : nullptr;
+    double part = 0.0;
+    float vmax = 0.0f;
+    auto emit = [&](int c, int rb, const float (&y)[4]) {
+      float v[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        float yy = y[e];
+        const int r = rb + e;
+        if (a.stage == 1)
+          yy = (c == 0 && r == 0) ? 0.0f
+                                  : (float)((double)yy / (d.tabM->lam_split[c] + d.tabN->lam_split[r]));
+        if (a.stage == 3) {
+          const size_t o = (size_t)c * R + r;
+          if (iso && iso[o]) yy = 0.0f;
+          part += (double)rv[o] * (double)yy;
+        }
+        v[e] = yy;
+        vmax = fmaxf(vmax, fabsf(yy));
+      }
+      *reinterpret_cast<float4*>(Out + (size_t)c * R + rb) = make_float4(v[0], v[1], v[2], v[3]);
+    };
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int c = t.c0 + wc + j * 16 + lr;
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int rb = t.r0 + wr + i * 16 + (lane >> 4) * 4;
+        if (!inverse) {
+          const float y[4] = {U[i][j][0] * inv_xs, U[i][j][1] * inv_xs, U[i][j][2] * inv_xs,
+                              U[i][j][3] * inv_xs};
+          emit(c, rb, y);
+        } else {
+          const float yp[4] = {(U[i][j][0] + V[i][j][0]) * inv_xs, (U[i][j][1] + V[i][j][1]) * inv_xs,
+                               (U[i][j][2] + V[i][j][2]) * inv_xs, (U[i][j][3] + V[i][j][3]) * inv_xs};
+          const float ym[4] = {(U[i][j][0] - V[i][j][0]) * inv_xs, (U[i][j][1] - V[i][j][1]) * inv_xs,
+                               (U[i][j][2] - V[i][j][2]) * inv_xs, (U[i][j][3] - V[i][j][3]) * inv_xs};
+          emit(c, rb, yp);
+          emit(n - 1 - c, rb, ym);
+        }
+      }
+    }
+    if (!SPLIT && a.stage < 3) {
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) vmax = fmaxf(vmax, __shfl_down(vmax, off, 64));
+      if (lane == 0)
+        atomicMax(reinterpret_cast<unsigned int*>(&st.amax[a.stage + 1]), __float_as_uint(vmax));
+    }
+    if (a.stage == 3) {
+      double vv[1] = {part};
+      block_sum<1>(vv, red);
+      if (tid == 0) a.P[1 * a.pstride + g] = vv[0];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // FMA stage (FP64 path, FP32 option): 64 x 64 tile, 16 x 16 threads x 4 x 4.
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -326,11 +520,14 @@ void e_dct_stage(hipStream_t st, const Engine& e, int ndtiles, int stage, int ex
   a.stage = stage;
   a.expect = expect;
   const int grid = std::max(1, std::min(ndtiles, 2048));
-  // kind: 0 FP64 FMA, 1 FP32 FMA, 2 split-bf16 MFMA, 3 scaled-fp16 MFMA
+  // kind: 0 FP64 FMA, 1 FP32 FMA, 2 split-bf16 MFMA, 3 scaled-fp16 MFMA;
+  // +2 (kinds 4, 5): the even/odd MFMA kernels (every side a multiple of 128)
   if (kind == 0) hipLaunchKernelGGL(k_e_dct_fma<double>, dim3(grid), dim3(256), 0, st, a);
   else if (kind == 1) hipLaunchKernelGGL(k_e_dct_fma<float>, dim3(grid), dim3(256), 0, st, a);
   else if (kind == 2) hipLaunchKernelGGL(k_e_dct_mfma<1>, dim3(grid), dim3(256), 0, st, a);
-  else hipLaunchKernelGGL(k_e_dct_mfma<0>, dim3(grid), dim3(256), 0, st, a);
+  else if (kind == 3) hipLaunchKernelGGL(k_e_dct_mfma<0>, dim3(grid), dim3(256), 0, st, a);
+  else if (kind == 4) hipLaunchKernelGGL(k_e_dct_sym<1>, dim3(grid), dim3(256), 0, st, a);
+  else hipLaunchKernelGGL(k_e_dct_sym<0>, dim3(grid), dim3(256), 0, st, a);
 }
 
 // ---------------------------------------------------------------------------

@@ -49,6 +49,17 @@ struct DctTables {
   uint16_t* c_h = nullptr;    // fp16 C
   uint16_t* ct_h = nullptr;   // fp16 C^T
   double* lam = nullptr;      // 2 - 2 cos(pi k / n)
+  // Even/odd factorisation (n a multiple of 128, h = n/2): spectra are kept
+  // in split order (even k first, then odd k).
+  //   EO  (n x h): row c < h is C[2c][0..h), row h + c is C[2c+1][0..h)
+  //   EOt (h x n): row j is [C[0][j], C[2][j], ..., C[1][j], C[3][j], ...]
+  uint16_t* eo_hi = nullptr;
+  uint16_t* eo_lo = nullptr;
+  uint16_t* eo_h = nullptr;
+  uint16_t* eot_hi = nullptr;
+  uint16_t* eot_lo = nullptr;
+  uint16_t* eot_h = nullptr;
+  double* lam_split = nullptr;  // eigenvalues in split order
 };
 
 // HIP-event timing of selected kernel classes (instrumentation).

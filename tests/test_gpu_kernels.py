@@ -175,6 +175,21 @@ def test_precond_mixed(ctx, oracle, pc, mode, rel, M, N, hole):
     assert err <= rel, (pc, mode, err)
 
 
+@pytest.mark.parametrize("mode,rel", [("split_bf16", 2e-4), ("fp16_scaled", 1e-2)])
+@pytest.mark.parametrize("M,N", [(128, 128), (128, 384), (256, 128), (384, 256)])
+@pytest.mark.parametrize("hole", [False, True])
+def test_precond_dct_even_odd(ctx, oracle, mode, rel, M, N, hole):
+    """Sides that are multiples of 128 take the even/odd MFMA kernels (spectra
+    in split order): same result as the dense definition."""
+    U, V, r = _precond_case(oracle, M, N, 41, hole)
+    U32_, V32_, r32 = (a.astype(np.float32).astype(np.float64) for a in (U, V, r))
+    ref = oracle.Preconditioner("dct", U32_, V32_).apply(r32)
+    s = host(ctx.precond_apply(dev(U32_, torch.float32), dev(V32_, torch.float32),
+                               dev(r32, torch.float32), "dct", precision="mixed", dct_mode=mode))
+    err = np.abs(s - ref).max() / np.abs(ref).max()
+    assert err <= rel, (mode, M, N, err)
+
+
 def test_mfma_operand_layout(ctx, oracle):
     """A DCT stage contraction on a structured input whose every output element
     depends on a distinct (row, column) pair: a wrong MFMA lane mapping would

@@ -340,6 +340,29 @@ def test_deterministic(ctx):
 # ---------------------------------------------------------------------------
 # Batch
 # ---------------------------------------------------------------------------
+@pytest.mark.parametrize("mode", ["split_bf16", "fp16_scaled"])
+def test_batch_even_odd_dct(ctx, oracle, mode):
+    """A batch whose sides are multiples of 128 (even/odd DCT kernels): every
+    map reaches relres 1e-6, agrees with its own single solve bit for bit, and
+    stays within the accuracy the FP64 oracle has at the same tolerance."""
+    shapes = [(128, 256), (256, 128), (128, 128), (384, 256)]
+    maps = synth.batch_maps(sides=shapes, seed=91)
+    psis = [dev(p) for p, _ in maps]
+    phis, rc, stats = ctx.batch(psis, p=0.0, preconditioner="dct", precision="mixed",
+                                dct_mode=mode, k_max=5, outer_tol=0.0)
+    for k, (p, _) in enumerate(maps):
+        assert stats[k]["final_relres"] <= 1e-6
+        single = ctx.solve(dev(p), p=0.0, preconditioner="dct", precision="mixed",
+                           dct_mode=mode, k_max=5, outer_tol=0.0)
+        assert np.array_equal(host(phis[k]), host(single.phi))
+        ex = oracle.unwrap_exact(p, p=0.0, outer=5)
+        same_tol = oracle.unwrap(p, p=0.0, precond="dct", tol=1e-6, k_max=5, outer_tol=0.0)
+        d = maxdiff(host(phis[k]), ex.phi)
+        d_orc = maxdiff(same_tol.phi, ex.phi)
+        print("batch even/odd", mode, shapes[k], "maxdiff vs exact", d, "oracle", d_orc)
+        assert d <= max(3.0 * d_orc, 1e-5)
+
+
 @pytest.mark.parametrize("pc", ["jacobi", "dct"])
 def test_batch_matches_single(ctx, pc):
     shapes = [(64, 64), (37, 53), (128, 96), (16, 200)]
