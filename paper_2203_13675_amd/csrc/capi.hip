@@ -36,6 +36,7 @@ void KTimer::end(int idx, int cls, hipStream_t st) {
   if (idx < 0) return;
   if (events[idx + 1]) (void)hipEventRecord(events[idx + 1], st);
   pending.push_back({idx, idx + 1, cls});
+  n[cls] += 1;
 }
 
 void KTimer::flush() {

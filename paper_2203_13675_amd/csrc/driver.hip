@@ -115,7 +115,18 @@ static const DctTabDev* dct_dev(lp_unwrap_ctx* ctx, int n, int* status) {
 }
 
 // Lay out n maps; (re)allocate grow-only; upload descriptors and tile maps.
-static int engine_setup(lp_unwrap_ctx* ctx, int n, const lpu_map* maps, int elem, bool need_dct) {
+// DCT output tiles are 64 x 64 for the dense kernels and 128 x 64 for the
+// even/odd kernels (used when every side is a multiple of 128 in the mixed
+// path with MFMA transforms); the count per map is the same in all stages.
+static bool even_odd_ok(const lpu_map* maps, int n, bool mixed, int dct_mode) {
+  if (!mixed || dct_mode == LPU_DCT_FP32) return false;
+  for (int m = 0; m < n; ++m)
+    if (maps[m].rows % 128 != 0 || maps[m].cols % 128 != 0) return false;
+  return true;
+}
+
+static int engine_setup(lp_unwrap_ctx* ctx, int n, const lpu_map* maps, int elem, bool need_dct,
+                        int dct_trows = kDT) {
   Engine& e = ctx->eng;
   std::vector<MapDesc> hd(n);
   long long px = 0;
@@ -129,7 +140,7 @@ static int engine_setup(lp_unwrap_ctx* ctx, int n, const lpu_map* maps, int elem
     d.ntiles = d.tiles_x * ((d.M + kTH - 1) / kTH);
     d.tile0 = tiles;
     tiles += d.ntiles;
-    d.ndt = ((d.M + kDT - 1) / kDT) * ((d.N + kDT - 1) / kDT);
+    d.ndt = ((d.M + dct_trows - 1) / dct_trows) * ((d.N + kDT - 1) / kDT);
     d.dtile0 = dtiles;
     dtiles += d.ndt;
     d.off = px;
@@ -162,7 +173,8 @@ static int engine_setup(lp_unwrap_ctx* ctx, int n, const lpu_map* maps, int elem
     A((void**)&e.tile_map, 4 * (size_t)tiles);
     A((void**)&e.dtile_map, 4 * (size_t)dtiles);
     A((void**)&e.act, 4 * (size_t)tiles);
-    A((void**)&e.dact, 4 * (size_t)dtiles);
+    const long long dcap = (long long)dtiles + 8LL * (n + 1) * 256 + 64;
+    A((void**)&e.dact, 4 * (size_t)(2 * dcap));
     A((void**)&e.mact, 4 * (size_t)n);
     A((void**)&e.counts, 64);
     A((void**)&e.dx, 8 * (size_t)cpx);
@@ -176,8 +188,9 @@ static int engine_setup(lp_unwrap_ctx* ctx, int n, const lpu_map* maps, int elem
     A((void**)&e.P, 8 * (size_t)kNumSlots * pst);
     if (ok && hipHostMalloc((void**)&e.hms, sizeof(MapState) * n) != hipSuccess) ok = false;
     if (ok && hipHostMalloc((void**)&e.hcounts, 64) != hipSuccess) ok = false;
-    if (ok && hipHostMalloc((void**)&e.hlist, 4 * ((size_t)tiles + dtiles + n + 16)) != hipSuccess)
+    if (ok && hipHostMalloc((void**)&e.hlist, 4 * ((size_t)tiles + 2 * dcap + n + 16)) != hipSuccess)
       ok = false;
+    e.dlist_cap = dcap;
     if (!ok) {
       engine_free(e);
       return set_error(ctx, LPU_ERR_OOM, "engine allocation failed");
@@ -196,6 +209,7 @@ static int engine_setup(lp_unwrap_ctx* ctx, int n, const lpu_map* maps, int elem
   e.total_tiles = tiles;
   e.total_dtiles = dtiles;
   e.max_n = maxN;
+  e.dct_trows = dct_trows;
   e.hdesc = hd;
   hipStream_t st = ctx->stream;
   // descriptors and tile -> map tables (staged through the pinned list buffer)
@@ -225,21 +239,62 @@ static int engine_activate(lp_unwrap_ctx* ctx, const std::vector<int>& set, int*
   int nt = 0;
   for (int m : set)
     for (int t = 0; t < e.hdesc[m].ntiles; ++t) h[nt++] = e.hdesc[m].tile0 + t;
+  // DCT tiles, one list per stage parity (rows of X are the map's rows for
+  // stages 0 and 2, its columns for stages 1 and 3).  Blocks are dispatched
+  // round-robin over the 8 XCDs, so list position q runs on XCD q mod 8 (the
+  // grid is a multiple of 8).  All column tiles of one row block go to one
+  // XCD, consecutively, so the block's rows of X are re-read from that XCD's
+  // L2; row blocks are balanced over the XCDs largest first.  Unused slots
+  // hold -1.
   int* hd = h + nt;
-  int nd = 0;
-  for (int m : set)
-    for (int t = 0; t < e.hdesc[m].ndt; ++t) hd[nd++] = e.hdesc[m].dtile0 + t;
-  int* hm = hd + nd;
+  int ndl[2] = {0, 0};
+  for (int par = 0; par < 2; ++par) {
+    int* out = hd + par * e.dlist_cap;
+    struct Unit {
+      int tile0, tr, tc;
+      long long w;
+    };
+    std::vector<Unit> units;
+    for (int m : set) {
+      const MapDesc& d = e.hdesc[m];
+      const int R = par ? d.N : d.M, K = par ? d.M : d.N;
+      const int tr = (R + e.dct_trows - 1) / e.dct_trows, tc = (K + kDT - 1) / kDT;
+      for (int rt = 0; rt < tr; ++rt) units.push_back({d.dtile0 + rt, tr, tc, (long long)tc * K});
+    }
+    std::stable_sort(units.begin(), units.end(),
+                     [](const Unit& a, const Unit& b) { return a.w > b.w; });
+    std::vector<std::vector<int>> q(8);
+    long long load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (const Unit& u : units) {
+      int x = 0;
+      for (int k = 1; k < 8; ++k)
+        if (load[k] < load[x]) x = k;
+      for (int ct = 0; ct < u.tc; ++ct) q[x].push_back(u.tile0 + ct * u.tr);
+      load[x] += u.w;
+    }
+    size_t L = 0;
+    for (int x = 0; x < 8; ++x) L = std::max(L, q[x].size());
+    int len = 0;
+    for (size_t j = 0; j < L; ++j)
+      for (int x = 0; x < 8; ++x) out[len++] = j < q[x].size() ? q[x][j] : -1;
+    ndl[par] = len;
+  }
+  const int nd = std::max(ndl[0], ndl[1]);
+  int* hm = hd + 2 * e.dlist_cap;
   int nm = 0;
   for (int m : set) hm[nm++] = m;
   int* hc = hm + nm;
   hc[0] = nt;
-  hc[1] = nd;
+  hc[1] = ndl[0];
   hc[2] = nm;
+  hc[3] = ndl[1];
   if (nt) LPU_HIP_CHECK(ctx, hipMemcpyAsync(e.act, h, 4 * (size_t)nt, hipMemcpyHostToDevice, st));
-  if (nd) LPU_HIP_CHECK(ctx, hipMemcpyAsync(e.dact, hd, 4 * (size_t)nd, hipMemcpyHostToDevice, st));
+  for (int par = 0; par < 2; ++par)
+    if (ndl[par])
+      LPU_HIP_CHECK(ctx, hipMemcpyAsync(e.dact + par * e.dlist_cap, hd + par * e.dlist_cap,
+                                        4 * (size_t)ndl[par], hipMemcpyHostToDevice, st));
   if (nm) LPU_HIP_CHECK(ctx, hipMemcpyAsync(e.mact, hm, 4 * (size_t)nm, hipMemcpyHostToDevice, st));
-  LPU_HIP_CHECK(ctx, hipMemcpyAsync(e.counts, hc, 12, hipMemcpyHostToDevice, st));
+  LPU_HIP_CHECK(ctx, hipMemcpyAsync(e.counts, hc, 16, hipMemcpyHostToDevice, st));
   LPU_HIP_CHECK(ctx, hipEventRecord(ctx->list_event, st));
   ctx->list_event_live = true;
   *ntiles = nt;
@@ -394,7 +449,8 @@ static int run_maps(lp_unwrap_ctx* ctx, int n, const lpu_map* maps, double p, do
   const double t_start = now_ms();
   hipStream_t st = ctx->stream;
   const bool mixed = sizeof(T) == 4;
-  int rc = engine_setup(ctx, n, maps, (int)sizeof(T), pc == kPcDct);
+  int rc = engine_setup(ctx, n, maps, (int)sizeof(T), pc == kPcDct,
+                        even_odd_ok(maps, n, mixed, o.dct_mode) ? 128 : kDT);
   if (rc) return rc;
   Engine& e = ctx->eng;
   KTimer& kt = ctx->kt;
@@ -609,14 +665,15 @@ int engine_solve(lp_unwrap_ctx* ctx, int n, const lpu_map* maps, double p, doubl
 // Step entry points: one map through the engine's kernels
 // ---------------------------------------------------------------------------
 static int step_setup(lp_unwrap_ctx* ctx, int M, int N, int elem, bool dct, const double* psi,
-                      const float* mask, double* phi) {
+                      const float* mask, double* phi, int dct_mode = LPU_DCT_FP32) {
   lpu_map mp;
   mp.rows = M;
   mp.cols = N;
   mp.psi = psi;
   mp.mask = mask;
   mp.phi = phi;
-  int rc = engine_setup(ctx, 1, &mp, elem, dct);
+  const bool eo = dct && even_odd_ok(&mp, 1, elem == 4, dct_mode);
+  int rc = engine_setup(ctx, 1, &mp, elem, dct, eo ? 128 : kDT);
   if (rc) return rc;
   std::vector<int> one(1, 0);
   int nt, nd;
@@ -701,7 +758,7 @@ int step_pivots(lp_unwrap_ctx* ctx, int M, int N, const T* U, const T* V, T* piv
 template <typename T>
 int step_precond(lp_unwrap_ctx* ctx, int M, int N, int pc, int dct_mode, double omega, const T* U,
                  const T* V, const T* r, T* s) {
-  int rc = step_setup(ctx, M, N, sizeof(T), pc == kPcDct, nullptr, nullptr, nullptr);
+  int rc = step_setup(ctx, M, N, sizeof(T), pc == kPcDct, nullptr, nullptr, nullptr, dct_mode);
   if (rc) return rc;
   Engine& e = ctx->eng;
   hipStream_t st = ctx->stream;

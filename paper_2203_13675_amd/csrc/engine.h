@@ -86,9 +86,12 @@ struct Engine {
   int* tile_map = nullptr;   // global stencil tile -> map
   int* dtile_map = nullptr;  // global DCT tile -> map
   int* act = nullptr;        // active stencil tiles
-  int* dact = nullptr;       // active DCT tiles
+  int* dact = nullptr;       // active DCT tiles: two XCD-ordered lists (see driver)
+  long long dlist_cap = 0;   // capacity of each of the two DCT lists
+  int dct_trows = kDT;       // DCT output tile rows (64 dense, 128 even/odd)
   int* mact = nullptr;       // active maps (sweep kernels)
-  int* counts = nullptr;     // [0] active tiles, [1] active DCT tiles, [2] active maps
+  int* counts = nullptr;     // [0] active tiles, [1] DCT list (even stages), [2] active
+                             // maps, [3] DCT list (odd stages)
   int* hcounts = nullptr;    // pinned
   int* hlist = nullptr;      // pinned staging for the lists
   // FP64 arrays

@@ -37,6 +37,8 @@ struct DArgs {
   const void* rvec;
   const unsigned char* iso;
   int stage, expect;
+  int trows;  // output tile rows: 64 (dense kernels) or 128 (even/odd kernels)
+  int cidx;   // counts[] slot holding the length of `dact`
 };
 
 struct DTile {
@@ -54,9 +56,9 @@ __device__ __forceinline__ DTile dtile(const DArgs& a, int g) {
   const bool rows_m = (a.stage & 1) == 0;
   t.R = rows_m ? d.M : d.N;
   t.K = rows_m ? d.N : d.M;
-  const int tiles_r = (t.R + kDT - 1) / kDT;
+  const int tiles_r = (t.R + a.trows - 1) / a.trows;
   const int local = g - d.dtile0;
-  t.r0 = (local % tiles_r) * kDT;
+  t.r0 = (local % tiles_r) * a.trows;
   t.c0 = (local / tiles_r) * kDT;
   t.off = d.off;
   t.tab = rows_m ? d.tabN : d.tabM;
@@ -104,10 +106,11 @@ __device__ __forceinline__ float fp16_scale(float amax) {
 template <int SPLIT>
 __global__ void __launch_bounds__(256) k_e_dct_mfma(DArgs a) {
   __shared__ double red[4];
-  const int nact = a.counts[1];
+  const int nact = a.counts[a.cidx];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int t_ = blockIdx.x; t_ < nact; t_ += gridDim.x) {
     const int g = a.dact[t_];
+    if (g < 0) continue;  // padding slot of the XCD-ordered list
     const DTile t = dtile(a, g);
     if (!t.ok) continue;  // uniform over the block
     const int R = t.R, K = t.K;
@@ -239,122 +242,131 @@ __global__ void __launch_bounds__(256) k_e_dct_mfma(DArgs a) {
 //   inverse  u = E^T X_even, v = O^T X_odd;  x[j] = u_j + v_j,
 //            x[n-1-j] = u_j - v_j  (j < h).
 // Both halve the multiply-adds of the dense transform.  A block owns a
-// 64 x 64 output tile (inverse: columns c < h, writing c and n-1-c); X
+// 128 x 64 output tile (inverse: columns c < h, writing c and n-1-c); wave w
+// computes rows 64 (w & 1) .. +63 and columns 32 (w >> 1) .. +31 as 4 x 2
+// MFMA 16x16 tiles, i.e. 65 flop per LDS byte read with the bf16 split.  X
 // (converted once to bf16 hi/lo or scaled fp16) and the table slice are
-// staged in double-buffered LDS, the next K step is fetched into registers
+// staged in double-buffered LDS; the next K step is fetched into registers
 // while the MFMAs of the current one run.
 // ---------------------------------------------------------------------------
 constexpr int kLp = 40;  // LDS row pitch in 16-bit elements (32 + 8 padding)
 
-template <int SPLIT>
+template <int SPLIT, int INV>
 __global__ void __launch_bounds__(256) k_e_dct_sym(DArgs a) {
-  __shared__ __attribute__((aligned(16))) uint16_t Xh[2][64][kLp];
-  __shared__ __attribute__((aligned(16))) uint16_t Xl[2][64][kLp];
+  constexpr int L2 = SPLIT ? 2 : 1;  // lo planes exist only for the bf16 split
+  __shared__ __attribute__((aligned(16))) uint16_t Xh[2][128][kLp];
+  __shared__ __attribute__((aligned(16))) uint16_t Xl[L2][SPLIT ? 128 : 1][kLp];
   __shared__ __attribute__((aligned(16))) uint16_t Bh[2][64][kLp];
-  __shared__ __attribute__((aligned(16))) uint16_t Bl[2][64][kLp];
+  __shared__ __attribute__((aligned(16))) uint16_t Bl[L2][SPLIT ? 64 : 1][kLp];
   __shared__ double red[4];
-  const int nact = a.counts[1];
+  const int nact = a.counts[a.cidx];
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-  const int lrow = tid >> 2, lk = (tid & 3) * 8;          // staging assignment
-  const int wr = (w & 1) * 32, wc = (w >> 1) * 32;         // wave sub-tile
-  const int lr = lane & 15, kg = (lane >> 4) * 8;          // MFMA operand lane map
-  const bool inverse = a.stage >= 2;
+  const int lrow = tid >> 2, lk = (tid & 3) * 8;  // staging: X rows lrow, lrow + 64; B row lrow
+  const int wr = (w & 1) * 64, wc = (w >> 1) * 32;  // wave sub-tile
+  const int lr = lane & 15, kg = (lane >> 4) * 8;   // MFMA operand lane map
   for (int t_ = blockIdx.x; t_ < nact; t_ += gridDim.x) {
     const int g = a.dact[t_];
+    if (g < 0) continue;  // padding slot of the XCD-ordered list
     const DTile t = dtile(a, g);
     if (!t.ok) continue;  // uniform over the block
     const int R = t.R, n = t.K, h = n >> 1;
-    if (inverse && t.c0 >= h) {
+    if (INV && t.c0 >= h) {
       if (a.stage == 3 && tid == 0) a.P[1 * a.pstride + g] = 0.0;
       continue;
     }
     const float* X = reinterpret_cast<const float*>(a.X) + t.off;
     float* Out = reinterpret_cast<float*>(a.Out) + t.off;
-    const uint16_t* Th = inverse ? (SPLIT ? t.tab->eot_hi : t.tab->eot_h) : (SPLIT ? t.tab->eo_hi : t.tab->eo_h);
-    const uint16_t* Tl = inverse ? t.tab->eot_lo : t.tab->eo_lo;
-    const int tpitch = inverse ? n : h;
-    const float sign = (!inverse && t.c0 >= h) ? -1.0f : 1.0f;
-    const int keff = inverse ? n : h;
-    const int nsteps = keff / 32;
+    const uint16_t* Th = INV ? (SPLIT ? t.tab->eot_hi : t.tab->eot_h) : (SPLIT ? t.tab->eo_hi : t.tab->eo_h);
+    const uint16_t* Tl = INV ? t.tab->eot_lo : t.tab->eo_lo;
+    const int tpitch = INV ? n : h;
+    const float sign = (!INV && t.c0 >= h) ? -1.0f : 1.0f;
+    const int nsteps = (INV ? n : h) / 32;
     MapState& st = a.ms[t.m];
     float xs = 1.0f, inv_xs = 1.0f;
     if (!SPLIT) {
       float amax = a.stage == 0 ? (float)sqrt(st.rr) * 1.0000001f : st.amax[a.stage];
-      if (!inverse) amax *= 2.0f;  // x_a +- x_b
+      if (!INV) amax *= 2.0f;  // x_a +- x_b
       xs = fp16_scale(amax);
       inv_xs = 1.0f / xs;
     }
-    const float* xrow = X + (size_t)(t.r0 + lrow) * n;
+    const float* xrow[2] = {X + (size_t)(t.r0 + lrow) * n, X + (size_t)(t.r0 + lrow + 64) * n};
     const uint16_t* trow_h = Th + (size_t)(t.c0 + lrow) * tpitch;
     const uint16_t* trow_l = Tl + (size_t)(t.c0 + lrow) * tpitch;
-    // register staging of one K step
-    u16x8 sxh, sxl, sbh, sbl;
+    u16x8 sxh[2], sxl[2], sbh, sbl;
     auto fetch = [&](int k0) {
       const int k = k0 + lk;
-      const float4* pa = reinterpret_cast<const float4*>(xrow + k);
-      const float4 a0 = pa[0], a1 = pa[1];
-      float v[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
-      if (!inverse) {
-        const float4* pb = reinterpret_cast<const float4*>(xrow + (n - 8 - k));
-        const float4 b0 = pb[0], b1 = pb[1];
-        const float m[8] = {b1.w, b1.z, b1.y, b1.x, b0.w, b0.z, b0.y, b0.x};
 #pragma unroll
-        for (int e = 0; e < 8; ++e) v[e] += sign * m[e];
-      }
+      for (int q = 0; q < 2; ++q) {
+        const float4* pa = reinterpret_cast<const float4*>(xrow[q] + k);
+        const float4 a0 = pa[0], a1 = pa[1];
+        float v[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+        if (!INV) {
+          const float4* pb = reinterpret_cast<const float4*>(xrow[q] + (n - 8 - k));
+          const float4 b0 = pb[0], b1 = pb[1];
+          const float m[8] = {b1.w, b1.z, b1.y, b1.x, b0.w, b0.z, b0.y, b0.x};
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        if (SPLIT) {
-          const __bf16 hb = (__bf16)v[e];
-          sxh[e] = __builtin_bit_cast(uint16_t, hb);
-          sxl[e] = __builtin_bit_cast(uint16_t, (__bf16)(v[e] - (float)hb));
-        } else {
-          sxh[e] = __builtin_bit_cast(uint16_t, (_Float16)(v[e] * xs));
+          for (int e = 0; e < 8; ++e) v[e] += sign * m[e];
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          if (SPLIT) {
+            const __bf16 hb = (__bf16)v[e];
+            sxh[q][e] = __builtin_bit_cast(uint16_t, hb);
+            sxl[q][e] = __builtin_bit_cast(uint16_t, (__bf16)(v[e] - (float)hb));
+          } else {
+            sxh[q][e] = __builtin_bit_cast(uint16_t, (_Float16)(v[e] * xs));
+          }
         }
       }
       sbh = *reinterpret_cast<const u16x8*>(trow_h + k);
       if (SPLIT) sbl = *reinterpret_cast<const u16x8*>(trow_l + k);
     };
     auto stash = [&](int buf) {
-      *reinterpret_cast<u16x8*>(&Xh[buf][lrow][lk]) = sxh;
-      *reinterpret_cast<u16x8*>(&Bh[buf][lrow][lk]) = sbh;
-      if (SPLIT) {
-        *reinterpret_cast<u16x8*>(&Xl[buf][lrow][lk]) = sxl;
-        *reinterpret_cast<u16x8*>(&Bl[buf][lrow][lk]) = sbl;
-      }
-    };
-    f32x4 U[2][2], V[2][2];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+      for (int q = 0; q < 2; ++q) {
+        *reinterpret_cast<u16x8*>(&Xh[buf][lrow + 64 * q][lk]) = sxh[q];
+        if (SPLIT) *reinterpret_cast<u16x8*>(&Xl[SPLIT ? buf : 0][lrow + 64 * q][lk]) = sxl[q];
+      }
+      *reinterpret_cast<u16x8*>(&Bh[buf][lrow][lk]) = sbh;
+      if (SPLIT) *reinterpret_cast<u16x8*>(&Bl[SPLIT ? buf : 0][lrow][lk]) = sbl;
+    };
+    f32x4 U[4][2], V[4][2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int j = 0; j < 2; ++j) U[i][j] = V[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    __syncthreads();  // previous tile's readers are done with the buffers
+    __syncthreads();  // the previous tile's readers are done with the buffers
     fetch(0);
     stash(0);
     __syncthreads();
     for (int s = 0; s < nsteps; ++s) {
       const int buf = s & 1;
       if (s + 1 < nsteps) fetch((s + 1) * 32);
-      const bool second = inverse && (s * 32 >= h);  // accumulate v after the even half
+      const bool second = INV && (s * 32 >= h);  // odd half of the spectrum -> v
+      u16x8 bh[2], bl[2];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
+      for (int j = 0; j < 2; ++j) {
+        bh[j] = *reinterpret_cast<const u16x8*>(&Bh[buf][wc + j * 16 + lr][kg]);
+        if (SPLIT) bl[j] = *reinterpret_cast<const u16x8*>(&Bl[SPLIT ? buf : 0][wc + j * 16 + lr][kg]);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
         const u16x8 ah = *reinterpret_cast<const u16x8*>(&Xh[buf][wr + i * 16 + lr][kg]);
         u16x8 al;
-        if (SPLIT) al = *reinterpret_cast<const u16x8*>(&Xl[buf][wr + i * 16 + lr][kg]);
+        if (SPLIT) al = *reinterpret_cast<const u16x8*>(&Xl[SPLIT ? buf : 0][wr + i * 16 + lr][kg]);
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
-          const u16x8 bh = *reinterpret_cast<const u16x8*>(&Bh[buf][wc + j * 16 + lr][kg]);
           f32x4 acc = second ? V[i][j] : U[i][j];
           if (SPLIT) {
-            const u16x8 bl = *reinterpret_cast<const u16x8*>(&Bl[buf][wc + j * 16 + lr][kg]);
             acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, ah),
-                                                         __builtin_bit_cast(bf16x8, bh), acc, 0, 0, 0);
+                                                         __builtin_bit_cast(bf16x8, bh[j]), acc, 0, 0, 0);
             acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, ah),
-                                                         __builtin_bit_cast(bf16x8, bl), acc, 0, 0, 0);
+                                                         __builtin_bit_cast(bf16x8, bl[j]), acc, 0, 0, 0);
             acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, al),
-                                                         __builtin_bit_cast(bf16x8, bh), acc, 0, 0, 0);
+                                                         __builtin_bit_cast(bf16x8, bh[j]), acc, 0, 0, 0);
           } else {
             acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, ah),
-                                                        __builtin_bit_cast(f16x8, bh), acc, 0, 0, 0);
+                                                        __builtin_bit_cast(f16x8, bh[j]), acc, 0, 0, 0);
           }
           if (second) V[i][j] = acc;
           else U[i][j] = acc;
@@ -392,9 +404,9 @@ __global__ void __launch_bounds__(256) k_e_dct_sym(DArgs a) {
     for (int j = 0; j < 2; ++j) {
       const int c = t.c0 + wc + j * 16 + lr;
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
+      for (int i = 0; i < 4; ++i) {
         const int rb = t.r0 + wr + i * 16 + (lane >> 4) * 4;
-        if (!inverse) {
+        if (!INV) {
           const float y[4] = {U[i][j][0] * inv_xs, U[i][j][1] * inv_xs, U[i][j][2] * inv_xs,
                               U[i][j][3] * inv_xs};
           emit(c, rb, y);
@@ -430,11 +442,12 @@ __global__ void __launch_bounds__(256) k_e_dct_fma(DArgs a) {
   __shared__ T Xs[16][64 + 4];
   __shared__ T Bs[16][64 + 4];
   __shared__ double red[4];
-  const int nact = a.counts[1];
+  const int nact = a.counts[a.cidx];
   const int tid = threadIdx.x, tr = tid % 16, tc = tid / 16;
   const int lrow = tid / 4, lk = (tid % 4) * 4;
   for (int t_ = blockIdx.x; t_ < nact; t_ += gridDim.x) {
     const int g = a.dact[t_];
+    if (g < 0) continue;  // padding slot of the XCD-ordered list
     const DTile t = dtile(a, g);
     if (!t.ok) continue;
     const int R = t.R, K = t.K, r0 = t.r0, c0 = t.c0;
@@ -509,7 +522,8 @@ void e_dct_stage(hipStream_t st, const Engine& e, int ndtiles, int stage, int ex
   a.desc = e.desc;
   a.ms = e.ms;
   a.dtile_map = e.dtile_map;
-  a.dact = e.dact;
+  a.dact = e.dact + (stage & 1) * e.dlist_cap;
+  a.cidx = (stage & 1) ? 3 : 1;
   a.counts = e.counts;
   a.P = e.P;
   a.pstride = e.pstride;
@@ -519,15 +533,18 @@ void e_dct_stage(hipStream_t st, const Engine& e, int ndtiles, int stage, int ex
   a.iso = e.iso;
   a.stage = stage;
   a.expect = expect;
-  const int grid = std::max(1, std::min(ndtiles, 2048));
+  a.trows = kind >= 4 ? 128 : 64;
+  const int grid = std::max(8, std::min((ndtiles + 7) / 8 * 8, 2048));
   // kind: 0 FP64 FMA, 1 FP32 FMA, 2 split-bf16 MFMA, 3 scaled-fp16 MFMA;
   // +2 (kinds 4, 5): the even/odd MFMA kernels (every side a multiple of 128)
   if (kind == 0) hipLaunchKernelGGL(k_e_dct_fma<double>, dim3(grid), dim3(256), 0, st, a);
   else if (kind == 1) hipLaunchKernelGGL(k_e_dct_fma<float>, dim3(grid), dim3(256), 0, st, a);
   else if (kind == 2) hipLaunchKernelGGL(k_e_dct_mfma<1>, dim3(grid), dim3(256), 0, st, a);
   else if (kind == 3) hipLaunchKernelGGL(k_e_dct_mfma<0>, dim3(grid), dim3(256), 0, st, a);
-  else if (kind == 4) hipLaunchKernelGGL(k_e_dct_sym<1>, dim3(grid), dim3(256), 0, st, a);
-  else hipLaunchKernelGGL(k_e_dct_sym<0>, dim3(grid), dim3(256), 0, st, a);
+  else if (kind == 4 && stage < 2) hipLaunchKernelGGL((k_e_dct_sym<1, 0>), dim3(grid), dim3(256), 0, st, a);
+  else if (kind == 4) hipLaunchKernelGGL((k_e_dct_sym<1, 1>), dim3(grid), dim3(256), 0, st, a);
+  else if (stage < 2) hipLaunchKernelGGL((k_e_dct_sym<0, 0>), dim3(grid), dim3(256), 0, st, a);
+  else hipLaunchKernelGGL((k_e_dct_sym<0, 1>), dim3(grid), dim3(256), 0, st, a);
 }
 
 // ---------------------------------------------------------------------------

@@ -21,6 +21,13 @@ torch = pytest.importorskip("torch")
 
 from paper_2203_13675_amd import synth  # noqa: E402
 
+# Accuracy asked of the mixed-precision path: unwrapped phase (mean removed)
+# within 1e-4 rad of the FP64 answer when both stop at relative residual 1e-6.
+# A solve that stops just below 1e-6 can sit this far from the exact inner
+# solution on its own (the FP64 oracle often overshoots to far smaller
+# residuals on smooth maps), so the bound is max(3 x oracle error, 1e-4).
+TARGET_RAD = 1e-4
+
 
 @pytest.fixture(scope="module")
 def ctx():
@@ -196,7 +203,7 @@ def test_mixed_peaks64_vs_exact(ctx, oracle, pc, mode):
     d_orc = maxdiff(same_tol.phi, ex.phi)
     print(pc, mode, "maxdiff vs exact", d, "oracle at 1e-6 vs exact", d_orc, res.stats)
     assert res.stats["final_relres"] <= 1e-6
-    assert d <= max(3.0 * d_orc, 1e-5)
+    assert d <= max(3.0 * d_orc, TARGET_RAD)
 
 
 def test_mixed_matches_fp64_same_preconditioner(ctx):
@@ -360,7 +367,7 @@ def test_batch_even_odd_dct(ctx, oracle, mode):
         d = maxdiff(host(phis[k]), ex.phi)
         d_orc = maxdiff(same_tol.phi, ex.phi)
         print("batch even/odd", mode, shapes[k], "maxdiff vs exact", d, "oracle", d_orc)
-        assert d <= max(3.0 * d_orc, 1e-5)
+        assert d <= max(3.0 * d_orc, TARGET_RAD)
 
 
 @pytest.mark.parametrize("pc", ["jacobi", "dct"])
