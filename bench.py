@@ -8,9 +8,9 @@ psi already resident in HBM when the timed region starts.
 
 Prints one JSON line (rank 0) with the metric, the roofline of the dominant
 kernel (achieved = algorithmic bytes or flops of its launches / their summed
-HIP-event durations, measured on the library's stream inside the timed
-region), the plain-FP64 sequential comparison and the oracle's CPU rate on a
-bounded sample.
+HIP-event durations, measured on the library's stream in a timing pass over
+the same workload right after the timed region), the plain-FP64 sequential
+comparison and the oracle's CPU rate on a bounded sample.
 """
 from __future__ import annotations
 
@@ -42,6 +42,12 @@ def parse():
                     help="also time the plain FP64 sequential loop once (0: skip)")
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--profile", action="store_true", help="fewer steps, no extras (for rocprof)")
+    ap.add_argument("--graph", type=int, default=1, help="graph-captured PCG iterations (0: eager)")
+    ap.add_argument("--autotune", type=int, default=1,
+                    help="run the library's autotuner on the batch first (not timed)")
+    ap.add_argument("--tune-cache", default=None, help="autotuner cache file")
+    ap.add_argument("--calib-copy", type=int, default=0,
+                    help="MiB copied by a plain device copy after the run (counter calibration)")
     return ap.parse_args()
 
 
@@ -69,24 +75,34 @@ def main():
     def step():
         return ctx.batch(psis, phis=phis, options=o, **opts)
 
-    # warm-up with every kernel class timed: find the dominant class
-    ctx.kernel_timing("all")
+    tune = None
+    if a.autotune:
+        best, tune_ms = ctx.autotune(psis, phis=phis, options=o, probe_iters=20,
+                                     cache_path=a.tune_cache, **opts)
+        tune = {"tuning": best, "autotune_ms": tune_ms}
+    ctx.set_tuning(use_graph=a.graph)
+
     for _ in range(max(1, a.warmup)):
         step()
     torch.cuda.synchronize()
-    warm = ctx.kernel_timing_report()
-    dominant = max(warm.items(), key=lambda kv: kv[1]["ms"])[0] if warm else "spmv"
-    # timed region: only the dominant class carries events
-    ctx.kernel_timing(dominant)
+    # timed region: the production path, no instrumentation
     t0 = time.perf_counter()
     stats = None
     for _ in range(a.steps):
         _, rc, stats = step()
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / a.steps
+    # kernel timing pass: one more step of the same workload with every kernel
+    # class bracketed by HIP events on the library's stream (launch by launch:
+    # events cannot be read per replay inside a captured graph)
+    ctx.kernel_timing("all")
+    tk0 = time.perf_counter()
+    step()
+    torch.cuda.synchronize()
+    t_eager = time.perf_counter() - tk0
     ktimes = ctx.kernel_timing_report()
     ctx.kernel_timing("off")
-    warm_split = {k: v["ms"] / max(1, a.warmup) for k, v in warm.items()}
+    warm_split = {k: v["ms"] for k, v in ktimes.items()}
 
     value = total_px / dt / 1e6
     inner = sum(s["inner_iters_total"] for s in stats)
@@ -123,9 +139,13 @@ def main():
                                 "residual refinement" % a.dct_mode},
         "pcg_iters_per_step": inner, "cg_iters_per_s": inner / dt,
         "worst_final_relres": worst_relres,
-        "kernel_ms_per_step_warmup": warm_split,
+        "kernel_ms_per_step": warm_split,
+        "ms_per_step_timing_pass": t_eager * 1e3,
+        "issue": "graph" if a.graph else "eager",
         "roofline": roofline,
     }
+    if tune:
+        out["autotune"] = tune
 
     if a.fp64_compare and not a.profile:
         t0 = time.perf_counter()
@@ -137,6 +157,16 @@ def main():
         out["fp64_sequential"] = {"value": total_px / t64 / 1e6, "unit": "Mpixel/s",
                                   "seconds": t64}
         out["speedup_vs_fp64_sequential"] = out["value"] / out["fp64_sequential"]["value"]
+
+    if a.calib_copy > 0:
+        # plain copy of known size, for scaling the HBM byte counters
+        n = a.calib_copy * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calib_copy_bytes_each"] = 2 * n * 4
 
     if a.cpu_baseline and not a.profile:
         out["cpu_baseline"] = cpu_baseline(maps, shapes, a.outer)

@@ -241,6 +241,50 @@ int lpu_kernel_timing(lp_unwrap_ctx* ctx, unsigned int class_mask);
 int lpu_kernel_timing_get(lp_unwrap_ctx* ctx, int kernel_class, double* total_ms,
                           long long* launches, double* alg_bytes, double* alg_flops);
 
+/* ----------------------------------------------------------------------------
+ * Launch tuning.  None of these settings changes what is computed (Algorithm
+ * 1 and its arithmetic are the same); they change tile shapes, grid sizes and
+ * how the PCG iterations are issued.  Tile shape and grid size change the
+ * order in which FP64 partial sums of the dot products are added, so results
+ * may differ in the last bits between settings (bit-identical for repeated
+ * calls with one setting).
+ * ------------------------------------------------------------------------- */
+typedef struct lpu_tuning {
+    int tile_rows;        /* rows per stencil tile (one wave, 128 columns): 4, 8, 16, 32 or 64 */
+    int grid;             /* blocks of the grid-stride stencil kernels: 64 .. 65536            */
+    int dct_grid;         /* cap on the blocks of a DCT stage: 64 .. 65536                     */
+    int use_graph;        /* 1: issue each PCG iteration as one captured HIP graph launch      */
+    int max_batch_iters;  /* iterations issued between host reads of the map states: 2 .. 1024 */
+} lpu_tuning;
+
+/* Defaults: tile_rows 16, grid 4096, dct_grid 2048, use_graph 1,
+ * max_batch_iters 64. */
+void lpu_default_tuning(lpu_tuning* t);
+
+/* Replace / read the context's tuning.  Out-of-range fields give
+ * LPU_ERR_INVALID_ARG and leave the tuning unchanged. */
+int lp_unwrap_set_tuning(lp_unwrap_ctx* ctx, const lpu_tuning* t);
+int lp_unwrap_get_tuning(lp_unwrap_ctx* ctx, lpu_tuning* t);
+
+/* Autotuner: time candidate tunings on the given batch (same arguments as
+ * lp_unwrap_batch) and install the fastest on ctx.  Each candidate runs one
+ * outer iteration capped at `probe_iters` PCG iterations per map (a fixed
+ * amount of work for every candidate); the maps' phi arrays are overwritten
+ * (with use_phi0 = 0 semantics).  Coordinate search: tile_rows, then grid,
+ * then dct_grid, then use_graph.
+ *   cache_path  text file of "key tile_rows grid dct_grid use_graph
+ *               max_batch_iters" lines, or NULL.  The key covers the device
+ *               name, preconditioner, precision, DCT mode and the multiset of
+ *               map shapes.  A hit installs the stored tuning without timing;
+ *               a miss appends the winner.
+ *   best        [out] the installed tuning, may be NULL.
+ *   tune_ms     [out] wall time spent timing candidates (0 on a cache hit),
+ *               may be NULL.
+ * Returns LPU_OK or an error; the context keeps its previous tuning on error. */
+int lp_unwrap_autotune(lp_unwrap_ctx* ctx, int n_maps, const lpu_map* maps, double p, double eps,
+                       int preconditioner, double tol, const lpu_options* opts, int probe_iters,
+                       const char* cache_path, lpu_tuning* best, double* tune_ms);
+
 #ifdef __cplusplus
 }
 #endif

@@ -57,10 +57,20 @@ class LpuMap(ctypes.Structure):
                 ("mask", ctypes.c_void_p), ("phi", ctypes.c_void_p)]
 
 
+class LpuTuning(ctypes.Structure):
+    _fields_ = [("tile_rows", ctypes.c_int), ("grid", ctypes.c_int), ("dct_grid", ctypes.c_int),
+                ("use_graph", ctypes.c_int), ("max_batch_iters", ctypes.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 EXPORTED = ["lpu_default_options", "lp_unwrap_create", "lp_unwrap_destroy", "lp_unwrap_solve",
             "lp_unwrap_batch", "lp_unwrap_status_string", "lp_unwrap_last_error",
             "lpu_wrapped_differences", "lpu_weights", "lpu_apply_A", "lpu_rhs",
-            "lpu_precond_apply", "lpu_ilu_pivots", "lpu_kernel_timing", "lpu_kernel_timing_get"]
+            "lpu_precond_apply", "lpu_ilu_pivots", "lpu_kernel_timing", "lpu_kernel_timing_get",
+            "lpu_default_tuning", "lp_unwrap_set_tuning", "lp_unwrap_get_tuning",
+            "lp_unwrap_autotune"]
 
 # kernel classes of the instrumentation (lpu_kernel_class)
 KERNEL_CLASSES = {"spmv": 0, "update": 1, "confirm": 2, "init": 3, "dct": 4, "sweep": 5,
@@ -107,6 +117,16 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.lpu_kernel_timing_get.argtypes = [vp, ip, ctypes.POINTER(dp), ctypes.POINTER(ctypes.c_longlong),
                                           ctypes.POINTER(dp), ctypes.POINTER(dp)]
     lib.lpu_kernel_timing_get.restype = ip
+    lib.lpu_default_tuning.argtypes = [ctypes.POINTER(LpuTuning)]
+    lib.lpu_default_tuning.restype = None
+    lib.lp_unwrap_set_tuning.argtypes = [vp, ctypes.POINTER(LpuTuning)]
+    lib.lp_unwrap_set_tuning.restype = ip
+    lib.lp_unwrap_get_tuning.argtypes = [vp, ctypes.POINTER(LpuTuning)]
+    lib.lp_unwrap_get_tuning.restype = ip
+    lib.lp_unwrap_autotune.argtypes = [vp, ip, ctypes.POINTER(LpuMap), dp, dp, ip, dp,
+                                       ctypes.POINTER(LpuOptions), ip, ctypes.c_char_p,
+                                       ctypes.POINTER(LpuTuning), ctypes.POINTER(dp)]
+    lib.lp_unwrap_autotune.restype = ip
     return lib
 
 
@@ -229,13 +249,11 @@ class Context:
             self._raise(rc)
         return SolveResult(phi, rc, st.as_dict())
 
-    def batch(self, psis, masks=None, *, p=0.0, eps=0.01, preconditioner="dct", tol=1e-6,
-              options: LpuOptions | None = None, phis=None, check=True, **opt_kw):
+    @staticmethod
+    def _maps(psis, masks, phis):
         k = len(psis)
         if masks is None:
             masks = [None] * k
-        if options is None:
-            options = default_options(**opt_kw)
         if phis is None:
             phis = [torch.zeros(t.shape, dtype=torch.float64, device=t.device) for t in psis]
         arr = (LpuMap * k)()
@@ -246,6 +264,14 @@ class Context:
             _check_dev(ph, torch.float64, M * N, "phi")
             arr[i] = LpuMap(M, N, ps.data_ptr(), mk.data_ptr() if mk is not None else None,
                             ph.data_ptr())
+        return arr, phis
+
+    def batch(self, psis, masks=None, *, p=0.0, eps=0.01, preconditioner="dct", tol=1e-6,
+              options: LpuOptions | None = None, phis=None, check=True, **opt_kw):
+        k = len(psis)
+        if options is None:
+            options = default_options(**opt_kw)
+        arr, phis = self._maps(psis, masks, phis)
         stats = (LpuStats * k)()
         pc = PRECONDITIONERS[preconditioner] if isinstance(preconditioner, str) else preconditioner
         rc = self._lib.lp_unwrap_batch(self._h, k, arr, float(p), float(eps), pc, float(tol),
@@ -253,6 +279,43 @@ class Context:
         if check:
             self._raise(rc)
         return phis, rc, [s.as_dict() for s in stats]
+
+    # -- launch tuning ------------------------------------------------------
+    def tuning(self) -> dict:
+        t = LpuTuning()
+        self._raise(self._lib.lp_unwrap_get_tuning(self._h, ctypes.byref(t)))
+        return t.as_dict()
+
+    def set_tuning(self, **kw) -> dict:
+        """Change fields of the context's tuning (tile_rows, grid, dct_grid, use_graph,
+        max_batch_iters); "default" restores lpu_default_tuning."""
+        t = LpuTuning()
+        if kw.pop("default", False):
+            self._lib.lpu_default_tuning(ctypes.byref(t))
+        else:
+            self._raise(self._lib.lp_unwrap_get_tuning(self._h, ctypes.byref(t)))
+        for k, v in kw.items():
+            if k not in t.as_dict():
+                raise KeyError(k)
+            setattr(t, k, int(v))
+        self._raise(self._lib.lp_unwrap_set_tuning(self._h, ctypes.byref(t)))
+        return t.as_dict()
+
+    def autotune(self, psis, masks=None, *, p=0.0, eps=0.01, preconditioner="dct", tol=1e-6,
+                 options: LpuOptions | None = None, probe_iters=20, cache_path=None, phis=None,
+                 **opt_kw):
+        """Run lp_unwrap_autotune on a batch; returns (tuning dict, tuning wall ms)."""
+        if options is None:
+            options = default_options(**opt_kw)
+        arr, phis = self._maps(psis, masks, phis)
+        best, ms = LpuTuning(), ctypes.c_double()
+        pc = PRECONDITIONERS[preconditioner] if isinstance(preconditioner, str) else preconditioner
+        path = None if cache_path is None else str(cache_path).encode()
+        rc = self._lib.lp_unwrap_autotune(self._h, len(psis), arr, float(p), float(eps), pc,
+                                          float(tol), ctypes.byref(options), int(probe_iters),
+                                          path, ctypes.byref(best), ctypes.byref(ms))
+        self._raise(rc)
+        return best.as_dict(), ms.value
 
     # -- instrumentation ----------------------------------------------------
     def kernel_timing(self, classes="all"):

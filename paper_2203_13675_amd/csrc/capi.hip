@@ -135,6 +135,15 @@ void lpu_default_options(lpu_options* o) {
   o->max_refine = 30;
 }
 
+void lpu_default_tuning(lpu_tuning* t) {
+  if (!t) return;
+  t->tile_rows = kTH;
+  t->grid = kEngineGrid;
+  t->dct_grid = kDctGrid;
+  t->use_graph = 1;
+  t->max_batch_iters = 64;
+}
+
 int lp_unwrap_create(lp_unwrap_ctx** out, int device, void* stream, int max_rows, int max_cols) {
   if (!out || max_rows < 0 || max_cols < 0) return LPU_ERR_INVALID_ARG;
   *out = nullptr;
@@ -145,7 +154,13 @@ int lp_unwrap_create(lp_unwrap_ctx** out, int device, void* stream, int max_rows
   lp_unwrap_ctx* ctx = new lp_unwrap_ctx();
   ctx->device = device;
   ctx->stream = (hipStream_t)stream;
+  lpu_default_tuning(&ctx->tune);
   if (hipEventCreateWithFlags(&ctx->list_event, hipEventDisableTiming) != hipSuccess) {
+    delete ctx;
+    return LPU_ERR_HIP;
+  }
+  if (hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipEventDestroy(ctx->list_event);
     delete ctx;
     return LPU_ERR_HIP;
   }
@@ -163,7 +178,30 @@ void lp_unwrap_destroy(lp_unwrap_ctx* ctx) {
   free_dct_tables(ctx);
   ctx->kt.destroy();
   if (ctx->list_event) (void)hipEventDestroy(ctx->list_event);
+  if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   delete ctx;
+}
+
+int lp_unwrap_set_tuning(lp_unwrap_ctx* ctx, const lpu_tuning* t) {
+  if (!ctx || !t) return LPU_ERR_INVALID_ARG;
+  ctx->last_error.clear();
+  const int tr = t->tile_rows;
+  if (tr != 4 && tr != 8 && tr != 16 && tr != 32 && tr != 64)
+    return set_error(ctx, LPU_ERR_INVALID_ARG, "tile_rows must be 4, 8, 16, 32 or 64");
+  if (t->grid < 64 || t->grid > 65536) return set_error(ctx, LPU_ERR_INVALID_ARG, "grid outside [64, 65536]");
+  if (t->dct_grid < 64 || t->dct_grid > 65536)
+    return set_error(ctx, LPU_ERR_INVALID_ARG, "dct_grid outside [64, 65536]");
+  if (t->use_graph != 0 && t->use_graph != 1) return set_error(ctx, LPU_ERR_INVALID_ARG, "use_graph not 0/1");
+  if (t->max_batch_iters < 2 || t->max_batch_iters > 1024)
+    return set_error(ctx, LPU_ERR_INVALID_ARG, "max_batch_iters outside [2, 1024]");
+  ctx->tune = *t;
+  return LPU_OK;
+}
+
+int lp_unwrap_get_tuning(lp_unwrap_ctx* ctx, lpu_tuning* t) {
+  if (!ctx || !t) return LPU_ERR_INVALID_ARG;
+  *t = ctx->tune;
+  return LPU_OK;
 }
 
 const char* lp_unwrap_status_string(int s) {

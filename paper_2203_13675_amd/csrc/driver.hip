@@ -34,6 +34,8 @@ void e_finish(hipStream_t st, const Engine& e, int op, int expect, int mode, boo
               bool tail_single);
 void e_dct_stage(hipStream_t st, const Engine& e, int ndtiles, int stage, int expect, int kind,
                  const void* X, void* Out, const void* rvec);
+int egrid(const Engine& e, int ntiles);
+int dct_grid_for(const Engine& e, int ndtiles);
 template <typename T> void e_pivots(hipStream_t, const Engine&, int, int, bool, double);
 template <typename T>
 void e_sweep(hipStream_t, const Engine&, int, int, int, bool, double, const void*, void*, void*);
@@ -76,7 +78,16 @@ static void engine_free(Engine& e) {
   e = Engine();
 }
 
-void engine_release(lp_unwrap_ctx* ctx) { engine_free(ctx->eng); }
+void release_graphs(lp_unwrap_ctx* ctx) {
+  for (GraphEntry& g : ctx->graphs)
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  ctx->graphs.clear();
+}
+
+void engine_release(lp_unwrap_ctx* ctx) {
+  release_graphs(ctx);
+  engine_free(ctx->eng);
+}
 
 static const DctTabDev* dct_dev(lp_unwrap_ctx* ctx, int n, int* status) {
   const DctTables* t = get_dct_tables(ctx, n, status);
@@ -128,6 +139,7 @@ static bool even_odd_ok(const lpu_map* maps, int n, bool mixed, int dct_mode) {
 static int engine_setup(lp_unwrap_ctx* ctx, int n, const lpu_map* maps, int elem, bool need_dct,
                         int dct_trows = kDT) {
   Engine& e = ctx->eng;
+  release_graphs(ctx);  // captured graphs hold the previous layout's launch shapes
   std::vector<MapDesc> hd(n);
   long long px = 0;
   int tiles = 0, dtiles = 0, maxN = 1;
@@ -136,8 +148,9 @@ static int engine_setup(lp_unwrap_ctx* ctx, int n, const lpu_map* maps, int elem
     std::memset(&d, 0, sizeof(d));
     d.M = maps[m].rows;
     d.N = maps[m].cols;
+    d.th = ctx->tune.tile_rows;
     d.tiles_x = (d.N + kTW - 1) / kTW;
-    d.ntiles = d.tiles_x * ((d.M + kTH - 1) / kTH);
+    d.ntiles = d.tiles_x * ((d.M + d.th - 1) / d.th);
     d.tile0 = tiles;
     tiles += d.ntiles;
     d.ndt = ((d.M + dct_trows - 1) / dct_trows) * ((d.N + kDT - 1) / kDT);
@@ -209,6 +222,9 @@ static int engine_setup(lp_unwrap_ctx* ctx, int n, const lpu_map* maps, int elem
   e.total_tiles = tiles;
   e.total_dtiles = dtiles;
   e.max_n = maxN;
+  e.th = ctx->tune.tile_rows;
+  e.grid = ctx->tune.grid;
+  e.dct_grid = ctx->tune.dct_grid;
   e.dct_trows = dct_trows;
   e.hdesc = hd;
   hipStream_t st = ctx->stream;
@@ -329,9 +345,8 @@ struct Pcg {
 
   bool pointwise() const { return pc == kPcNone || pc == kPcJacobi; }
 
-  void tail(int ndt, int nmaps, int expect) {
+  void tail(hipStream_t st, int ndt, int nmaps, int expect) {
     Engine& e = ctx->eng;
-    hipStream_t st = ctx->stream;
     KTimer& kt = ctx->kt;
     if (pc == kPcDct) {
       const void* in[4] = {e.r, e.t1, e.t2, e.t1};
@@ -348,9 +363,67 @@ struct Pcg {
     }
   }
 
-  void fin(int op, int expect, int mode = kFinishNone) {
+  void fin(hipStream_t st, int op, int expect, int mode = kFinishNone) {
     const bool single = !(pc == kPcDct);
-    e_finish(ctx->stream, ctx->eng, op, expect, mode, pointwise(), single);
+    e_finish(st, ctx->eng, op, expect, mode, pointwise(), single);
+  }
+
+  // One PCG iteration for every running map of the active set (Algorithm 1's
+  // inner loop body): direction update + SpMV, alpha, x/r update, beta or
+  // stop test, preconditioner.
+  void body(hipStream_t st, int nt, int nd, int nm) {
+    Engine& e = ctx->eng;
+    KTimer& kt = ctx->kt;
+    int ev = kt.begin(LPU_KC_SPMV, st);
+    e_spmv<T>(st, e, nt, pc);
+    kt.end(ev, LPU_KC_SPMV, st);
+    fin(st, kFinAlphaH, kRun);
+    ev = kt.begin(LPU_KC_UPDATE, st);
+    e_update<T>(st, e, nt, pc);
+    kt.end(ev, LPU_KC_UPDATE, st);
+    fin(st, kFinUpdateH, kRun);
+    if (!pointwise()) {
+      tail(st, nd, nm, kRun);
+      fin(st, kFinTailH, kRun, kFinishIter);
+    }
+  }
+
+  // Issue K iterations: as K launches of a captured graph of the body (one
+  // graph per launch shape, cached for this engine layout), or launch by
+  // launch while kernel timing is on.
+  int iterate(int nt, int nd, int nm, long long K) {
+    hipStream_t st = ctx->stream;
+    if (!ctx->tune.use_graph || ctx->kt.mask != 0) {
+      for (long long k = 0; k < K; ++k) body(st, nt, nd, nm);
+      return LPU_OK;
+    }
+    const Engine& e = ctx->eng;
+    const int key[6] = {egrid(e, nt), pointwise() ? 0 : dct_grid_for(e, nd), nm, pc, dct_kind,
+                        (int)sizeof(T)};
+    hipGraphExec_t ex = nullptr;
+    for (const GraphEntry& g : ctx->graphs)
+      if (std::equal(key, key + 6, g.key)) ex = g.exec;
+    if (!ex) {
+      hipStream_t cs = ctx->cap_stream;
+      LPU_HIP_CHECK(ctx, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+      body(cs, nt, nd, nm);
+      hipGraph_t g = nullptr;
+      LPU_HIP_CHECK(ctx, hipStreamEndCapture(cs, &g));
+      const hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (ie != hipSuccess)
+        return set_error(ctx, LPU_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+      if (ctx->graphs.size() >= 16) {
+        (void)hipGraphExecDestroy(ctx->graphs.front().exec);
+        ctx->graphs.erase(ctx->graphs.begin());
+      }
+      GraphEntry ge;
+      std::copy(key, key + 6, ge.key);
+      ge.exec = ex;
+      ctx->graphs.push_back(ge);
+    }
+    for (long long k = 0; k < K; ++k) LPU_HIP_CHECK(ctx, hipGraphLaunch(ex, st));
+    return LPU_OK;
   }
 
   // Run PCG for the maps in `set` from x0; per-map tol2 already in hms.
@@ -379,40 +452,28 @@ struct Pcg {
     int ev = kt.begin(LPU_KC_INIT, st);
     e_resid<T>(st, e, nt, pc, false);
     kt.end(ev, LPU_KC_INIT, st);
-    fin(kFinInitH, kRun);
+    fin(st, kFinInitH, kRun);
     if (!pw) {
-      tail(nd, (int)set.size(), kInitPc);
-      fin(kFinTailH, kInitPc, kFinishInit);
+      tail(st, nd, (int)set.size(), kInitPc);
+      fin(st, kFinTailH, kInitPc, kFinishInit);
     }
     long long K = 4;
+    const long long Kcap = std::max(2, ctx->tune.max_batch_iters);
     std::vector<double> prev_metric(e.n_maps, -1.0);
     std::vector<long long> prev_l(e.n_maps, 0);
     for (;;) {
-      for (long long k = 0; k < K; ++k) {
-        ev = kt.begin(LPU_KC_SPMV, st);
-        e_spmv<T>(st, e, nt, pc);
-        kt.end(ev, LPU_KC_SPMV, st);
-        fin(kFinAlphaH, kRun);
-        ev = kt.begin(LPU_KC_UPDATE, st);
-        e_update<T>(st, e, nt, pc);
-        kt.end(ev, LPU_KC_UPDATE, st);
-        fin(kFinUpdateH, kRun);
-        if (!pw) {
-          tail(nd, (int)set.size(), kRun);
-          fin(kFinTailH, kRun, kFinishIter);
-        }
-      }
+      if ((rc = iterate(nt, nd, (int)set.size(), K))) return rc;
       ev = kt.begin(LPU_KC_CONFIRM, st);
       e_resid<T>(st, e, nt, pc, true);
       kt.end(ev, LPU_KC_CONFIRM, st);
-      fin(kFinConfirmH, kConfirm);
+      fin(st, kFinConfirmH, kConfirm);
       if (!pw) {
-        tail(nd, (int)set.size(), kConfirmPc);
-        fin(kFinTailH, kConfirmPc, kFinishConfirm);
+        tail(st, nd, (int)set.size(), kConfirmPc);
+        fin(st, kFinTailH, kConfirmPc, kFinishConfirm);
       }
       if ((rc = read_states(ctx))) return rc;
       std::vector<int> still;
-      long long nextK = 64;
+      long long nextK = Kcap;
       for (int m : set) {
         const MapState& s = e.hms[m];
         if (s.state == kDone || s.state == kCap || s.state == kBreakdown) continue;
@@ -434,7 +495,7 @@ struct Pcg {
         set = still;
         if ((rc = engine_activate(ctx, set, &nt, &nd))) return rc;
       }
-      K = std::max(2LL, std::min(nextK, 64LL));
+      K = std::max(2LL, std::min(nextK, Kcap));
     }
     return LPU_OK;
   }

@@ -20,9 +20,10 @@
 namespace lpu {
 
 constexpr int kTW = 128;  // stencil tile width (columns): two per lane of one wave
-constexpr int kTH = 16;   // stencil tile height (rows), marched by the wave
+constexpr int kTH = 16;   // default stencil tile height (rows), marched by the wave
 constexpr int kDT = 64;   // DCT output tile (64 x 64)
-constexpr int kEngineGrid = 4096;  // blocks of the grid-stride tile kernels
+constexpr int kEngineGrid = 4096;  // default cap on the blocks of the grid-stride tile kernels
+constexpr int kDctGrid = 2048;     // default cap on the blocks of a DCT stage
 constexpr int kNumSlots = 4;       // partial-sum slots
 
 // DCT tables of one size n as seen by the kernels.
@@ -51,6 +52,7 @@ struct DctTabDev {
 
 struct MapDesc {
   int M, N;
+  int th;                     // stencil tile height (rows)
   int tiles_x, ntiles, tile0;  // stencil tiles
   int ndt, dtile0;             // DCT tiles (same count in every stage)
   int use_iso;                 // zero the preconditioner output on isolated pixels
@@ -79,6 +81,9 @@ struct Engine {
   long long total_px = 0, cap_px = 0;
   int total_tiles = 0, total_dtiles = 0, cap_tiles = 0, cap_dtiles = 0;
   int max_n = 1;             // widest map (sweep kernels)
+  int th = kTH;              // stencil tile height (rows)
+  int grid = kEngineGrid;    // cap on the blocks of the stencil tile kernels
+  int dct_grid = kDctGrid;   // cap on the blocks of a DCT stage (multiple of 8)
   std::vector<MapDesc> hdesc;
   MapDesc* desc = nullptr;
   MapState* ms = nullptr;

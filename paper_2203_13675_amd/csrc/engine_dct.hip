@@ -516,6 +516,15 @@ __global__ void __launch_bounds__(256) k_e_dct_fma(DArgs a) {
   }
 }
 
+// Grid of a DCT stage: the next power of two >= the list length, capped; a
+// multiple of 8, so list position q always runs on XCD q mod 8.
+int dct_grid_for(const Engine& e, int ndtiles) {
+  const int cap = std::max(8, e.dct_grid / 8 * 8);
+  int g = 8;
+  while (g < ndtiles && g < cap) g <<= 1;
+  return std::min(g, cap);
+}
+
 void e_dct_stage(hipStream_t st, const Engine& e, int ndtiles, int stage, int expect, int kind,
                  const void* X, void* Out, const void* rvec) {
   DArgs a;
@@ -534,7 +543,7 @@ void e_dct_stage(hipStream_t st, const Engine& e, int ndtiles, int stage, int ex
   a.stage = stage;
   a.expect = expect;
   a.trows = kind >= 4 ? 128 : 64;
-  const int grid = std::max(8, std::min((ndtiles + 7) / 8 * 8, 2048));
+  const int grid = dct_grid_for(e, ndtiles);
   // kind: 0 FP64 FMA, 1 FP32 FMA, 2 split-bf16 MFMA, 3 scaled-fp16 MFMA;
   // +2 (kinds 4, 5): the even/odd MFMA kernels (every side a multiple of 128)
   if (kind == 0) hipLaunchKernelGGL(k_e_dct_fma<double>, dim3(grid), dim3(256), 0, st, a);

@@ -42,7 +42,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 struct TilePos {
-  int m, i0, j0, M, N;
+  int m, i0, j0, M, N, rows;
   long long off;
 };
 
@@ -53,7 +53,8 @@ __device__ __forceinline__ TilePos tile_pos(const MapDesc* __restrict__ desc,
   const MapDesc& d = desc[t.m];
   const int lt = g - d.tile0;
   const int ty = lt / d.tiles_x;
-  t.i0 = ty * kTH;
+  t.rows = d.th;
+  t.i0 = ty * d.th;
   t.j0 = (lt - ty * d.tiles_x) * kTW;
   t.M = d.M;
   t.N = d.N;
@@ -102,7 +103,7 @@ __device__ __forceinline__ T stencil5(T uw, T uc, T vn, T vc, T xc, T xw, T xe, 
 
 // March the tile: for every interior pixel call epi(i, j, x_ij, (A x)_ij),
 // where the operand x is given by field(i, j) (zero outside the grid).
-template <typename T, typename F, typename E>
+template <int TH, typename T, typename F, typename E>
 __device__ __forceinline__ void march_stencil(const TilePos& tp, const T* __restrict__ U,
                                               const T* __restrict__ V, F field, E epi) {
   const int M = tp.M, N = tp.N, i0 = tp.i0, j0 = tp.j0, l = lane_id();
@@ -117,10 +118,8 @@ __device__ __forceinline__ void march_stencil(const TilePos& tp, const T* __rest
   R2<T> xm = frow(i0 - 1), xc = frow(i0);
   T xh = field(i0, hj);
   R2<T> vn = ldrow(V, i0 - 1, j0, M, N);
-#pragma unroll 4
-  for (int k = 0; k < kTH; ++k) {
+  auto step = [&](int k) {
     const int i = i0 + k;
-    if (i >= M) break;
     const R2<T> xp = frow(i + 1);
     const T xph = field(i + 1, hj);
     const R2<T> uc = ldrow(U, i, j0, M, N);
@@ -137,6 +136,18 @@ __device__ __forceinline__ void march_stencil(const TilePos& tp, const T* __rest
     xc = xp;
     xh = xph;
     vn = vc;
+  };
+  // TH > 0: compile-time tile height, unrolled (the lane shuffles inside keep
+  // the compiler from unrolling a loop of run-time length); TH == 0: tp.rows
+  if constexpr (TH > 0) {
+#pragma unroll 4
+    for (int k = 0; k < TH; ++k) {
+      if (i0 + k >= M) break;
+      step(k);
+    }
+  } else {
+    const int kend = min(tp.rows, M - i0);
+    for (int k = 0; k < kend; ++k) step(k);
   }
 }
 
@@ -144,9 +155,9 @@ __device__ __forceinline__ void march_stencil(const TilePos& tp, const T* __rest
 template <typename E>
 __device__ __forceinline__ void march_points(const TilePos& tp, E epi) {
   const int l = lane_id();
-  for (int k = 0; k < kTH; ++k) {
+  const int kend = min(tp.rows, tp.M - tp.i0);
+  for (int k = 0; k < kend; ++k) {
     const int i = tp.i0 + k;
-    if (i >= tp.M) break;
     const int ca = tp.j0 + l, cb = tp.j0 + 64 + l;
     if (ca < tp.N) epi(i, ca);
     if (cb < tp.N) epi(i, cb);
@@ -393,7 +404,7 @@ __global__ void __launch_bounds__(64) k_e_resid(EArgs A) {
     T* d0 = vec<T>(A.d0, tp.off);
     const int M = tp.M, N = tp.N;
     double srr = 0.0, srs = 0.0, sbb = 0.0;
-    march_stencil<T>(tp, U, V, [&](int i, int j) { return ldz(x, i, j, M, N); },
+    march_stencil<0, T>(tp, U, V, [&](int i, int j) { return ldz(x, i, j, M, N); },
                      [&](int i, int j, T, T ax) {
                        const size_t p = (size_t)i * N + j;
                        const T bv = b[p];
@@ -417,7 +428,7 @@ __global__ void __launch_bounds__(64) k_e_resid(EArgs A) {
 }
 
 // spmv: d_new = s + beta d_old; q = A d_new; partial d^T q
-template <typename T, int PC>
+template <typename T, int PC, int TH>
 __global__ void __launch_bounds__(64) k_e_spmv(EArgs A) {
   TILE_LOOP(A) {
     const int g = A.act[t_];
@@ -435,7 +446,7 @@ __global__ void __launch_bounds__(64) k_e_spmv(EArgs A) {
     T* q = vec<T>(A.q, tp.off);
     const int M = tp.M, N = tp.N;
     double sdq = 0.0;
-    march_stencil<T>(
+    march_stencil<TH, T>(
         tp, U, V,
         [&](int i, int j) {
           if (i < 0 || i >= M || j < 0 || j >= N) return T(0);
@@ -456,7 +467,7 @@ __global__ void __launch_bounds__(64) k_e_spmv(EArgs A) {
 
 // update: x_new = x_old + alpha d; r -= alpha q, or r = b - A x_new when
 // l is a multiple of the replacement period; pointwise s; partials r.r, r.s
-template <typename T, int PC>
+template <typename T, int PC, int TH>
 __global__ void __launch_bounds__(64) k_e_update(EArgs A) {
   TILE_LOOP(A) {
     const int g = A.act[t_];
@@ -478,7 +489,7 @@ __global__ void __launch_bounds__(64) k_e_update(EArgs A) {
     const int M = tp.M, N = tp.N;
     double srr = 0.0, srs = 0.0;
     if (replace) {
-      march_stencil<T>(
+      march_stencil<TH, T>(
           tp, U, V,
           [&](int i, int j) {
             if (i < 0 || i >= M || j < 0 || j >= N) return T(0);
@@ -525,7 +536,7 @@ __global__ void __launch_bounds__(64) k_e_apply(EArgs A) {
     const T* x = cvec<T>(A.s, tp.off);
     T* y = vec<T>(A.q, tp.off);
     const int M = tp.M, N = tp.N;
-    march_stencil<T>(tp, U, V, [&](int i, int j) { return ldz(x, i, j, M, N); },
+    march_stencil<0, T>(tp, U, V, [&](int i, int j) { return ldz(x, i, j, M, N); },
                      [&](int i, int j, T, T ax) { y[(size_t)i * N + j] = ax; });
   }
 }
@@ -666,8 +677,13 @@ __global__ void __launch_bounds__(256) k_e_finish(const MapDesc* __restrict__ de
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
-static inline int egrid(const Engine& e, int ntiles) {
-  return std::max(1, std::min(ntiles, kEngineGrid));
+// Grid of the tile kernels: the next power of two >= the active tiles, capped
+// (blocks stride over the list, so any grid is correct; few distinct shapes
+// keep captured graphs reusable as the active set shrinks).
+int egrid(const Engine& e, int ntiles) {
+  int g = 1;
+  while (g < ntiles && g < e.grid) g <<= 1;
+  return std::max(1, std::min(g, e.grid));
 }
 
 EArgs make_args(const Engine& e) {
@@ -740,24 +756,41 @@ void e_resid(hipStream_t st, const Engine& e, int ntiles, int pc, bool confirm) 
   else e_resid_pc<T, kPcNone>(st, e, ntiles, confirm);
 }
 
+template <typename T, int PC>
+static void e_spmv_pc(hipStream_t st, const Engine& e, int gr) {
+  switch (e.th) {
+    case 4: hipLaunchKernelGGL((k_e_spmv<T, PC, 4>), dim3(gr), dim3(64), 0, st, make_args(e)); break;
+    case 8: hipLaunchKernelGGL((k_e_spmv<T, PC, 8>), dim3(gr), dim3(64), 0, st, make_args(e)); break;
+    case 16: hipLaunchKernelGGL((k_e_spmv<T, PC, 16>), dim3(gr), dim3(64), 0, st, make_args(e)); break;
+    case 32: hipLaunchKernelGGL((k_e_spmv<T, PC, 32>), dim3(gr), dim3(64), 0, st, make_args(e)); break;
+    default: hipLaunchKernelGGL((k_e_spmv<T, PC, 0>), dim3(gr), dim3(64), 0, st, make_args(e)); break;
+  }
+}
+
 template <typename T>
 void e_spmv(hipStream_t st, const Engine& e, int ntiles, int pc) {
   const int gr = egrid(e, ntiles);
-  if (pc == kPcNone)
-    hipLaunchKernelGGL((k_e_spmv<T, kPcNone>), dim3(gr), dim3(64), 0, st, make_args(e));
-  else if (pc == kPcJacobi)
-    hipLaunchKernelGGL((k_e_spmv<T, kPcJacobi>), dim3(gr), dim3(64), 0, st, make_args(e));
-  else
-    hipLaunchKernelGGL((k_e_spmv<T, kPcDct>), dim3(gr), dim3(64), 0, st, make_args(e));
+  if (pc == kPcNone) e_spmv_pc<T, kPcNone>(st, e, gr);
+  else if (pc == kPcJacobi) e_spmv_pc<T, kPcJacobi>(st, e, gr);
+  else e_spmv_pc<T, kPcDct>(st, e, gr);
+}
+
+template <typename T, int PC>
+static void e_update_pc(hipStream_t st, const Engine& e, int gr) {
+  switch (e.th) {
+    case 4: hipLaunchKernelGGL((k_e_update<T, PC, 4>), dim3(gr), dim3(64), 0, st, make_args(e)); break;
+    case 8: hipLaunchKernelGGL((k_e_update<T, PC, 8>), dim3(gr), dim3(64), 0, st, make_args(e)); break;
+    case 16: hipLaunchKernelGGL((k_e_update<T, PC, 16>), dim3(gr), dim3(64), 0, st, make_args(e)); break;
+    case 32: hipLaunchKernelGGL((k_e_update<T, PC, 32>), dim3(gr), dim3(64), 0, st, make_args(e)); break;
+    default: hipLaunchKernelGGL((k_e_update<T, PC, 0>), dim3(gr), dim3(64), 0, st, make_args(e)); break;
+  }
 }
 
 template <typename T>
 void e_update(hipStream_t st, const Engine& e, int ntiles, int pc) {
   const int gr = egrid(e, ntiles);
-  if (pc == kPcJacobi)
-    hipLaunchKernelGGL((k_e_update<T, kPcJacobi>), dim3(gr), dim3(64), 0, st, make_args(e));
-  else
-    hipLaunchKernelGGL((k_e_update<T, kPcNone>), dim3(gr), dim3(64), 0, st, make_args(e));
+  if (pc == kPcJacobi) e_update_pc<T, kPcJacobi>(st, e, gr);
+  else e_update_pc<T, kPcNone>(st, e, gr);
 }
 
 template <typename T>

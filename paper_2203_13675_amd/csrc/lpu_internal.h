@@ -95,11 +95,25 @@ struct KTimer {
 
 #include "engine.h"
 
+namespace lpu {
+
+// Executable graph of one PCG iteration for one launch shape; valid until the
+// engine is laid out again (the cache is emptied by every engine set-up).
+struct GraphEntry {
+  int key[6];
+  hipGraphExec_t exec;
+};
+
+}  // namespace lpu
+
 struct lp_unwrap_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
+  hipStream_t cap_stream = nullptr;  // private stream used only to capture graphs
   std::string last_error;
+  lpu_tuning tune;
   lpu::Engine eng;
+  std::vector<lpu::GraphEntry> graphs;  // small cache, emptied by every engine set-up
   std::deque<lpu::DctTables> dct;  // cached per size (deque: stable references)
   std::vector<std::pair<int, lpu::DctTabDev*>> dct_dev;
   hipEvent_t list_event = nullptr;  // last upload from the pinned list staging
@@ -122,6 +136,7 @@ const DctTables* get_dct_tables(lp_unwrap_ctx* ctx, int n, int* status);
 void free_dct_tables(lp_unwrap_ctx* ctx);
 
 // engine (driver.hip)
+void release_graphs(lp_unwrap_ctx* ctx);
 int engine_solve(lp_unwrap_ctx* ctx, int n, const lpu_map* maps, double p, double tau, int pc,
                  double tol, const lpu_options& o, lpu_stats* stats);
 void engine_release(lp_unwrap_ctx* ctx);

@@ -62,7 +62,7 @@ def test_struct_layouts_match_header():
     from paper_2203_13675_amd import binding
     text = open(HEADER).read()
     for cls, cname in ((binding.LpuOptions, "lpu_options"), (binding.LpuStats, "lpu_stats"),
-                       (binding.LpuMap, "lpu_map")):
+                       (binding.LpuMap, "lpu_map"), (binding.LpuTuning, "lpu_tuning")):
         body = re.search(r"typedef struct %s \{(.*?)\} %s;" % (cname, cname), text, re.S).group(1)
         body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
         fields = []
@@ -76,3 +76,11 @@ def test_struct_layouts_match_header():
                 names = " ".join(parts[2:])
             fields += [x.strip() for x in names.split(",")]
         assert [f for f, _ in cls._fields_] == fields, (cname, fields)
+
+
+def test_default_tuning(lib):
+    from paper_2203_13675_amd import binding
+    t = binding.LpuTuning()
+    lib.lpu_default_tuning(ctypes.byref(t))
+    assert t.as_dict() == {"tile_rows": 16, "grid": 4096, "dct_grid": 2048, "use_graph": 1,
+                           "max_batch_iters": 64}
