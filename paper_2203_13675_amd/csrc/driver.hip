@@ -126,9 +126,10 @@ static const DctTabDev* dct_dev(lp_unwrap_ctx* ctx, int n, int* status) {
 }
 
 // Lay out n maps; (re)allocate grow-only; upload descriptors and tile maps.
-// DCT output tiles are 64 x 64 for the dense kernels and 128 x 64 for the
-// even/odd kernels (used when every side is a multiple of 128 in the mixed
-// path with MFMA transforms); the count per map is the same in all stages.
+// DCT output tiles are 64 x 64 for the dense kernels; the even/odd kernels
+// (used when every side is a multiple of 128 in the mixed path with MFMA
+// transforms) take 128 rows x 64 output pairs.  The count per map is the same
+// in all stages.
 static bool even_odd_ok(const lpu_map* maps, int n, bool mixed, int dct_mode) {
   if (!mixed || dct_mode == LPU_DCT_FP32) return false;
   for (int m = 0; m < n; ++m)
@@ -153,7 +154,9 @@ static int engine_setup(lp_unwrap_ctx* ctx, int n, const lpu_map* maps, int elem
     d.ntiles = d.tiles_x * ((d.M + d.th - 1) / d.th);
     d.tile0 = tiles;
     tiles += d.ntiles;
-    d.ndt = ((d.M + dct_trows - 1) / dct_trows) * ((d.N + kDT - 1) / kDT);
+    // even/odd tiles (128 rows) cover 64 output pairs, i.e. 128 columns of n
+    const int ccols = dct_trows == 128 ? 128 : kDT;
+    d.ndt = ((d.M + dct_trows - 1) / dct_trows) * ((d.N + ccols - 1) / ccols);
     d.dtile0 = dtiles;
     dtiles += d.ndt;
     d.off = px;
@@ -274,7 +277,8 @@ static int engine_activate(lp_unwrap_ctx* ctx, const std::vector<int>& set, int*
     for (int m : set) {
       const MapDesc& d = e.hdesc[m];
       const int R = par ? d.N : d.M, K = par ? d.M : d.N;
-      const int tr = (R + e.dct_trows - 1) / e.dct_trows, tc = (K + kDT - 1) / kDT;
+      const int ccols = e.dct_trows == 128 ? 128 : kDT;
+      const int tr = (R + e.dct_trows - 1) / e.dct_trows, tc = (K + ccols - 1) / ccols;
       for (int rt = 0; rt < tr; ++rt) units.push_back({d.dtile0 + rt, tr, tc, (long long)tc * K});
     }
     std::stable_sort(units.begin(), units.end(),

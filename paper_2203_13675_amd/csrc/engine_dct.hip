@@ -241,46 +241,55 @@ __global__ void __launch_bounds__(256) k_e_dct_mfma(DArgs a) {
 //            even/odd rows of C restricted to j < h;
 //   inverse  u = E^T X_even, v = O^T X_odd;  x[j] = u_j + v_j,
 //            x[n-1-j] = u_j - v_j  (j < h).
-// Both halve the multiply-adds of the dense transform.  A block owns a
-// 128 x 64 output tile (inverse: columns c < h, writing c and n-1-c); wave w
-// computes rows 64 (w & 1) .. +63 and columns 32 (w >> 1) .. +31 as 4 x 2
-// MFMA 16x16 tiles, i.e. 65 flop per LDS byte read with the bf16 split.  X
-// (converted once to bf16 hi/lo or scaled fp16) and the table slice are
-// staged in double-buffered LDS; the next K step is fetched into registers
-// while the MFMAs of the current one run.
+// Both halve the multiply-adds of the dense transform.
+//
+// A block owns 128 rows of X and 64 output columns c0 .. c0+63 of the half
+// range [0, h), in two halves computed side by side from the same loads:
+//   forward: half 0 = even outputs c (A = x_a + x_b), half 1 = odd outputs
+//            h + c (A = x_a - x_b);
+//   inverse: half 0 = u (spectrum columns [0, h)), half 1 = v (columns
+//            [h, n)), combined at the end into outputs c and n-1-c.
+// Wave w computes rows 64 (w & 1) .. +63 of half w >> 1 as 4 x 4 MFMA tiles
+// of 16 x 16 (64 accumulator registers).  Each K step of 32 stages both
+// halves of A (128 x 32) and of the table slice (64 x 32) in LDS, converted
+// once to bf16 hi/lo (or scaled fp16); the next step's global loads are in
+// flight while the MFMAs of the current one run.  LDS rows are 64 bytes
+// without padding; the 16-byte chunk q of row r sits at q ^ swz(r), which
+// keeps both the staging writes and the fragment reads free of bank conflicts.
 // ---------------------------------------------------------------------------
-constexpr int kLp = 40;  // LDS row pitch in 16-bit elements (32 + 8 padding)
+__device__ __forceinline__ int swz(int r) { return ((r >> 1) ^ (r >> 2)) & 3; }
+// offset (16-bit elements) of element 8q + e of LDS row r
+__device__ __forceinline__ int lds_at(int r, int q) { return r * 32 + ((q ^ swz(r)) << 3); }
+
+typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
 
 template <int SPLIT, int INV>
-__global__ void __launch_bounds__(256) k_e_dct_sym(DArgs a) {
-  constexpr int L2 = SPLIT ? 2 : 1;  // lo planes exist only for the bf16 split
-  __shared__ __attribute__((aligned(16))) uint16_t Xh[2][128][kLp];
-  __shared__ __attribute__((aligned(16))) uint16_t Xl[L2][SPLIT ? 128 : 1][kLp];
-  __shared__ __attribute__((aligned(16))) uint16_t Bh[2][64][kLp];
-  __shared__ __attribute__((aligned(16))) uint16_t Bl[L2][SPLIT ? 64 : 1][kLp];
+__global__ void __launch_bounds__(256, 2) k_e_dct_eo(DArgs a) {
+  constexpr int NP = SPLIT ? 2 : 1;                // hi (+ lo) planes
+  constexpr int kA = 128 * 32, kB = 64 * 32;       // elements of one A / B half-plane
+  constexpr int kStage = NP * 2 * (kA + kB) * 2;   // bytes of staged operands
+  constexpr int kXchg = 2 * 16 * 64 * 16;          // bytes of the inverse's v exchange
+  constexpr int kSmem = kStage > kXchg ? kStage : kXchg;
+  __shared__ __attribute__((aligned(16))) unsigned char smem[kSmem];
   __shared__ double red[4];
+  uint16_t* As = reinterpret_cast<uint16_t*>(smem);  // [plane][half][128 x 32]
+  uint16_t* Bs = As + NP * 2 * kA;                   // [plane][half][64 x 32]
   const int nact = a.counts[a.cidx];
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-  const int lrow = tid >> 2, lk = (tid & 3) * 8;  // staging: X rows lrow, lrow + 64; B row lrow
-  const int wr = (w & 1) * 64, wc = (w >> 1) * 32;  // wave sub-tile
-  const int lr = lane & 15, kg = (lane >> 4) * 8;   // MFMA operand lane map
+  const int wr = (w & 1) * 64, hf = w >> 1;
+  const int lr = lane & 15, kq = lane >> 4;        // MFMA operand map: row lr, k chunk kq
+  const int xr = tid >> 3, xk = (tid & 7) * 4;      // X staging: rows xr + 32 p, k xk .. +3
+  const int bseg = tid >> 2, bq = tid & 3;          // table staging: segment, 16-byte chunk
   for (int t_ = blockIdx.x; t_ < nact; t_ += gridDim.x) {
     const int g = a.dact[t_];
     if (g < 0) continue;  // padding slot of the XCD-ordered list
     const DTile t = dtile(a, g);
     if (!t.ok) continue;  // uniform over the block
-    const int R = t.R, n = t.K, h = n >> 1;
-    if (INV && t.c0 >= h) {
-      if (a.stage == 3 && tid == 0) a.P[1 * a.pstride + g] = 0.0;
-      continue;
-    }
+    const int R = t.R, n = t.K, h = n >> 1, c0 = t.c0;
     const float* X = reinterpret_cast<const float*>(a.X) + t.off;
     float* Out = reinterpret_cast<float*>(a.Out) + t.off;
-    const uint16_t* Th = INV ? (SPLIT ? t.tab->eot_hi : t.tab->eot_h) : (SPLIT ? t.tab->eo_hi : t.tab->eo_h);
-    const uint16_t* Tl = INV ? t.tab->eot_lo : t.tab->eo_lo;
-    const int tpitch = INV ? n : h;
-    const float sign = (!INV && t.c0 >= h) ? -1.0f : 1.0f;
-    const int nsteps = (INV ? n : h) / 32;
+    const uint16_t* T0 = INV ? (SPLIT ? t.tab->eot_hi : t.tab->eot_h) : (SPLIT ? t.tab->eo_hi : t.tab->eo_h);
+    const uint16_t* T1 = INV ? t.tab->eot_lo : t.tab->eo_lo;
     MapState& st = a.ms[t.m];
     float xs = 1.0f, inv_xs = 1.0f;
     if (!SPLIT) {
@@ -289,91 +298,106 @@ __global__ void __launch_bounds__(256) k_e_dct_sym(DArgs a) {
       xs = fp16_scale(amax);
       inv_xs = 1.0f / xs;
     }
-    const float* xrow[2] = {X + (size_t)(t.r0 + lrow) * n, X + (size_t)(t.r0 + lrow + 64) * n};
-    const uint16_t* trow_h = Th + (size_t)(t.c0 + lrow) * tpitch;
-    const uint16_t* trow_l = Tl + (size_t)(t.c0 + lrow) * tpitch;
-    u16x8 sxh[2], sxl[2], sbh, sbl;
+    // register staging of one K step
+    float4 sa[4], sb[4];
+    u16x8 sT[NP * 2];
     auto fetch = [&](int k0) {
-      const int k = k0 + lk;
 #pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        const float4* pa = reinterpret_cast<const float4*>(xrow[q] + k);
-        const float4 a0 = pa[0], a1 = pa[1];
-        float v[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
-        if (!INV) {
-          const float4* pb = reinterpret_cast<const float4*>(xrow[q] + (n - 8 - k));
-          const float4 b0 = pb[0], b1 = pb[1];
-          const float m[8] = {b1.w, b1.z, b1.y, b1.x, b0.w, b0.z, b0.y, b0.x};
+      for (int p = 0; p < 4; ++p) {
+        const float* row = X + (size_t)(t.r0 + xr + 32 * p) * n;
+        sa[p] = *reinterpret_cast<const float4*>(row + k0 + xk);
+        sb[p] = *reinterpret_cast<const float4*>(row + (INV ? h + k0 + xk : n - 4 - k0 - xk));
+      }
 #pragma unroll
-          for (int e = 0; e < 8; ++e) v[e] += sign * m[e];
-        }
+      for (int p = 0; p < NP * 2; ++p) {
+        const int s = p * 64 + bseg;                  // segment: ((half * NP) + plane) * 64 + row
+        const int half = s / (64 * NP), plane = (s / 64) % NP, row = s & 63;
+        const uint16_t* T = plane ? T1 : T0;
+        const uint16_t* src = INV ? T + (size_t)(c0 + row) * n + (half ? h : 0) + k0 + 8 * bq
+                                  : T + (size_t)((half ? h : 0) + c0 + row) * h + k0 + 8 * bq;
+        sT[p] = *reinterpret_cast<const u16x8*>(src);
+      }
+    };
+    auto stash = [&]() {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
+      for (int p = 0; p < 4; ++p) {
+        const int r = xr + 32 * p;
+        const float av[4] = {sa[p].x, sa[p].y, sa[p].z, sa[p].w};
+        // forward: the b part is x mirrored, x[n-1-k] for k = k0 + xk .. +3
+        const float bv[4] = {INV ? sb[p].x : sb[p].w, INV ? sb[p].y : sb[p].z,
+                             INV ? sb[p].z : sb[p].y, INV ? sb[p].w : sb[p].x};
+        u16x4 hv[2], lv[2];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const float v0 = INV ? av[e] : av[e] + bv[e];
+          const float v1 = INV ? bv[e] : av[e] - bv[e];
           if (SPLIT) {
-            const __bf16 hb = (__bf16)v[e];
-            sxh[q][e] = __builtin_bit_cast(uint16_t, hb);
-            sxl[q][e] = __builtin_bit_cast(uint16_t, (__bf16)(v[e] - (float)hb));
+            const __bf16 h0 = (__bf16)v0, h1 = (__bf16)v1;
+            hv[0][e] = __builtin_bit_cast(uint16_t, h0);
+            hv[1][e] = __builtin_bit_cast(uint16_t, h1);
+            lv[0][e] = __builtin_bit_cast(uint16_t, (__bf16)(v0 - (float)h0));
+            lv[1][e] = __builtin_bit_cast(uint16_t, (__bf16)(v1 - (float)h1));
           } else {
-            sxh[q][e] = __builtin_bit_cast(uint16_t, (_Float16)(v[e] * xs));
+            hv[0][e] = __builtin_bit_cast(uint16_t, (_Float16)(v0 * xs));
+            hv[1][e] = __builtin_bit_cast(uint16_t, (_Float16)(v1 * xs));
           }
         }
-      }
-      sbh = *reinterpret_cast<const u16x8*>(trow_h + k);
-      if (SPLIT) sbl = *reinterpret_cast<const u16x8*>(trow_l + k);
-    };
-    auto stash = [&](int buf) {
+        const int o = lds_at(r, xk >> 3) + (xk & 4);
 #pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        *reinterpret_cast<u16x8*>(&Xh[buf][lrow + 64 * q][lk]) = sxh[q];
-        if (SPLIT) *reinterpret_cast<u16x8*>(&Xl[SPLIT ? buf : 0][lrow + 64 * q][lk]) = sxl[q];
+        for (int half = 0; half < 2; ++half) {
+          *reinterpret_cast<u16x4*>(As + (0 * 2 + half) * kA + o) = hv[half];
+          if (SPLIT) *reinterpret_cast<u16x4*>(As + (1 * 2 + half) * kA + o) = lv[half];
+        }
       }
-      *reinterpret_cast<u16x8*>(&Bh[buf][lrow][lk]) = sbh;
-      if (SPLIT) *reinterpret_cast<u16x8*>(&Bl[SPLIT ? buf : 0][lrow][lk]) = sbl;
+#pragma unroll
+      for (int p = 0; p < NP * 2; ++p) {
+        const int s = p * 64 + bseg;
+        const int half = s / (64 * NP), plane = (s / 64) % NP, row = s & 63;
+        *reinterpret_cast<u16x8*>(Bs + (plane * 2 + half) * kB + lds_at(row, bq)) = sT[p];
+      }
     };
-    f32x4 U[4][2], V[4][2];
+    f32x4 acc[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j) U[i][j] = V[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    __syncthreads();  // the previous tile's readers are done with the buffers
+      for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int nsteps = h / 32;
     fetch(0);
-    stash(0);
-    __syncthreads();
     for (int s = 0; s < nsteps; ++s) {
-      const int buf = s & 1;
+      __syncthreads();  // readers of the previous step (or tile) are done
+      stash();
+      __syncthreads();
       if (s + 1 < nsteps) fetch((s + 1) * 32);
-      const bool second = INV && (s * 32 >= h);  // odd half of the spectrum -> v
-      u16x8 bh[2], bl[2];
+      const uint16_t* Ah = As + (0 * 2 + hf) * kA;
+      const uint16_t* Al = As + (1 * 2 + hf) * kA;
+      const uint16_t* Bh = Bs + (0 * 2 + hf) * kB;
+      const uint16_t* Bl = Bs + (1 * 2 + hf) * kB;
+      u16x8 bh[4], bl[4];
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        bh[j] = *reinterpret_cast<const u16x8*>(&Bh[buf][wc + j * 16 + lr][kg]);
-        if (SPLIT) bl[j] = *reinterpret_cast<const u16x8*>(&Bl[SPLIT ? buf : 0][wc + j * 16 + lr][kg]);
+      for (int j = 0; j < 4; ++j) {
+        bh[j] = *reinterpret_cast<const u16x8*>(Bh + lds_at(16 * j + lr, kq));
+        if (SPLIT) bl[j] = *reinterpret_cast<const u16x8*>(Bl + lds_at(16 * j + lr, kq));
       }
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const u16x8 ah = *reinterpret_cast<const u16x8*>(&Xh[buf][wr + i * 16 + lr][kg]);
+        const u16x8 ah = *reinterpret_cast<const u16x8*>(Ah + lds_at(wr + 16 * i + lr, kq));
         u16x8 al;
-        if (SPLIT) al = *reinterpret_cast<const u16x8*>(&Xl[SPLIT ? buf : 0][wr + i * 16 + lr][kg]);
+        if (SPLIT) al = *reinterpret_cast<const u16x8*>(Al + lds_at(wr + 16 * i + lr, kq));
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          f32x4 acc = second ? V[i][j] : U[i][j];
+        for (int j = 0; j < 4; ++j) {
           if (SPLIT) {
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, ah),
-                                                         __builtin_bit_cast(bf16x8, bh[j]), acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, ah),
-                                                         __builtin_bit_cast(bf16x8, bl[j]), acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, al),
-                                                         __builtin_bit_cast(bf16x8, bh[j]), acc, 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                __builtin_bit_cast(bf16x8, ah), __builtin_bit_cast(bf16x8, bh[j]), acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                __builtin_bit_cast(bf16x8, ah), __builtin_bit_cast(bf16x8, bl[j]), acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                __builtin_bit_cast(bf16x8, al), __builtin_bit_cast(bf16x8, bh[j]), acc[i][j], 0, 0, 0);
           } else {
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, ah),
-                                                        __builtin_bit_cast(f16x8, bh[j]), acc, 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
+                __builtin_bit_cast(f16x8, ah), __builtin_bit_cast(f16x8, bh[j]), acc[i][j], 0, 0, 0);
           }
-          if (second) V[i][j] = acc;
-          else U[i][j] = acc;
         }
       }
-      if (s + 1 < nsteps) stash(buf ^ 1);
-      __syncthreads();
     }
     // epilogue: lane holds D[row 4*(lane/16) + e][col lane mod 16] of each 16x16 tile
     const MapDesc& d = a.desc[t.m];
@@ -400,23 +424,43 @@ __global__ void __launch_bounds__(256) k_e_dct_sym(DArgs a) {
       }
       *reinterpret_cast<float4*>(Out + (size_t)c * R + rb) = make_float4(v[0], v[1], v[2], v[3]);
     };
+    if (!INV) {
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int c = t.c0 + wc + j * 16 + lr;
+      for (int j = 0; j < 4; ++j) {
+        const int c = (hf ? h : 0) + c0 + 16 * j + lr;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int rb = t.r0 + wr + i * 16 + (lane >> 4) * 4;
-        if (!INV) {
-          const float y[4] = {U[i][j][0] * inv_xs, U[i][j][1] * inv_xs, U[i][j][2] * inv_xs,
-                              U[i][j][3] * inv_xs};
-          emit(c, rb, y);
-        } else {
-          const float yp[4] = {(U[i][j][0] + V[i][j][0]) * inv_xs, (U[i][j][1] + V[i][j][1]) * inv_xs,
-                               (U[i][j][2] + V[i][j][2]) * inv_xs, (U[i][j][3] + V[i][j][3]) * inv_xs};
-          const float ym[4] = {(U[i][j][0] - V[i][j][0]) * inv_xs, (U[i][j][1] - V[i][j][1]) * inv_xs,
-                               (U[i][j][2] - V[i][j][2]) * inv_xs, (U[i][j][3] - V[i][j][3]) * inv_xs};
-          emit(c, rb, yp);
-          emit(n - 1 - c, rb, ym);
+        for (int i = 0; i < 4; ++i) {
+          const float y[4] = {acc[i][j][0] * inv_xs, acc[i][j][1] * inv_xs, acc[i][j][2] * inv_xs,
+                              acc[i][j][3] * inv_xs};
+          emit(c, t.r0 + wr + 16 * i + 4 * kq, y);
+        }
+      }
+    } else {
+      // v (half 1) goes through LDS to the waves holding u for the same rows
+      f32x4* xv = reinterpret_cast<f32x4*>(smem) + (size_t)(w & 1) * 16 * 64;
+      __syncthreads();  // every wave is done reading the staged operands
+      if (hf == 1) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) xv[(i * 4 + j) * 64 + lane] = acc[i][j];
+      }
+      __syncthreads();
+      if (hf == 0) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int c = c0 + 16 * j + lr;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const f32x4 v = xv[(i * 4 + j) * 64 + lane];
+            const float yp[4] = {(acc[i][j][0] + v[0]) * inv_xs, (acc[i][j][1] + v[1]) * inv_xs,
+                                 (acc[i][j][2] + v[2]) * inv_xs, (acc[i][j][3] + v[3]) * inv_xs};
+            const float ym[4] = {(acc[i][j][0] - v[0]) * inv_xs, (acc[i][j][1] - v[1]) * inv_xs,
+                                 (acc[i][j][2] - v[2]) * inv_xs, (acc[i][j][3] - v[3]) * inv_xs};
+            const int rb = t.r0 + wr + 16 * i + 4 * kq;
+            emit(c, rb, yp);
+            emit(n - 1 - c, rb, ym);
+          }
         }
       }
     }
@@ -550,10 +594,10 @@ void e_dct_stage(hipStream_t st, const Engine& e, int ndtiles, int stage, int ex
   else if (kind == 1) hipLaunchKernelGGL(k_e_dct_fma<float>, dim3(grid), dim3(256), 0, st, a);
   else if (kind == 2) hipLaunchKernelGGL(k_e_dct_mfma<1>, dim3(grid), dim3(256), 0, st, a);
   else if (kind == 3) hipLaunchKernelGGL(k_e_dct_mfma<0>, dim3(grid), dim3(256), 0, st, a);
-  else if (kind == 4 && stage < 2) hipLaunchKernelGGL((k_e_dct_sym<1, 0>), dim3(grid), dim3(256), 0, st, a);
-  else if (kind == 4) hipLaunchKernelGGL((k_e_dct_sym<1, 1>), dim3(grid), dim3(256), 0, st, a);
-  else if (stage < 2) hipLaunchKernelGGL((k_e_dct_sym<0, 0>), dim3(grid), dim3(256), 0, st, a);
-  else hipLaunchKernelGGL((k_e_dct_sym<0, 1>), dim3(grid), dim3(256), 0, st, a);
+  else if (kind == 4 && stage < 2) hipLaunchKernelGGL((k_e_dct_eo<1, 0>), dim3(grid), dim3(256), 0, st, a);
+  else if (kind == 4) hipLaunchKernelGGL((k_e_dct_eo<1, 1>), dim3(grid), dim3(256), 0, st, a);
+  else if (stage < 2) hipLaunchKernelGGL((k_e_dct_eo<0, 0>), dim3(grid), dim3(256), 0, st, a);
+  else hipLaunchKernelGGL((k_e_dct_eo<0, 1>), dim3(grid), dim3(256), 0, st, a);
 }
 
 // ---------------------------------------------------------------------------
