@@ -447,6 +447,7 @@ struct Pcg {
       s.l_max = lmax[k];
       s.period = period[k];
       s.rule = rule;
+      s.stall = sizeof(T) == 4 ? 1 : 0;  // refinement follows every mixed inner solve
       s.state = kRun;
     }
     if ((rc = write_states(ctx))) return rc;
@@ -480,7 +481,8 @@ struct Pcg {
       long long nextK = Kcap;
       for (int m : set) {
         const MapState& s = e.hms[m];
-        if (s.state == kDone || s.state == kCap || s.state == kBreakdown) continue;
+        if (s.state == kDone || s.state == kCap || s.state == kBreakdown || s.state == kStall)
+          continue;
         still.push_back(m);
         const double metric = rule == LPU_STOP_PAPER ? s.delta_new : s.rr;
         const double target = rule == LPU_STOP_PAPER ? s.thr_delta : s.thr_rr;

@@ -70,8 +70,9 @@ struct MapState {
   double alpha, beta;
   double dq, rr, bb, rs;
   double thr_rr, thr_delta, tol2, eps2;
+  double rr_chk;               // last true residual above the bound (stagnation test)
   long long l, l_max, period, nfinish;
-  int state, rule, replaced, pad;
+  int state, rule, replaced, stall;  // stall: 1 = stop when the true residual stagnates
   float amax[4];
 };
 

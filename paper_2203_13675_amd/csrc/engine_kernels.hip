@@ -583,6 +583,18 @@ __device__ inline void map_finish(MapState& s, int mode, double rs) {
   s.state = st;
 }
 
+// Stagnation of a mixed-precision inner solve: a true residual (a periodic
+// replacement or a failed confirmation) above the bound that is not at least
+// 10 % (in norm) below the previous one.  The FP32 iterate has then reached
+// what its precision can resolve; the FP64 refinement around the solve takes
+// over from the best iterate.
+__device__ inline bool stagnated(MapState& s, double rr_true) {
+  if (!s.stall || s.rule != LPU_STOP_RELRES || rr_true <= s.thr_rr) return false;
+  const bool stuck = s.rr_chk > 0.0 && rr_true >= 0.81 * s.rr_chk;
+  s.rr_chk = rr_true;
+  return stuck;
+}
+
 template <int NS>
 __device__ __forceinline__ void fin_sums(const double* __restrict__ P, long long pstride, int first,
                                          int count, const int* slots, double (&out)[NS],
@@ -647,7 +659,11 @@ __global__ void __launch_bounds__(256) k_e_finish(const MapDesc* __restrict__ de
       const bool replace = (s.l % s.period) == 0;
       s.rr = v[0];
       s.replaced = replace ? 1 : 0;
-      if (s.rule == LPU_STOP_RELRES && !replace && v[0] <= s.thr_rr) {
+      if (replace && stagnated(s, v[0])) {
+        s.delta_old = s.delta_new;
+        s.l += 1;
+        s.state = kStall;
+      } else if (s.rule == LPU_STOP_RELRES && !replace && v[0] <= s.thr_rr) {
         s.delta_old = s.delta_new;
         s.l += 1;
         s.state = kConfirm;
@@ -659,6 +675,7 @@ __global__ void __launch_bounds__(256) k_e_finish(const MapDesc* __restrict__ de
       s.rr = v[0];
       s.replaced = 1;
       if (v[0] <= s.thr_rr) s.state = kDone;
+      else if (stagnated(s, v[0])) s.state = kStall;
       else if (pointwise) map_finish(s, kFinishConfirm, v[1]);
       else s.state = kConfirmPc;
       break;

@@ -27,7 +27,8 @@ enum CgState : int {
   kInitPc = 3,     // initial residual formed, waiting for the preconditioner
   kDone = 4,       // stop rule met
   kCap = 5,        // l_max reached
-  kBreakdown = 6   // d^T A d <= 0 or non-finite scalars
+  kBreakdown = 6,  // d^T A d <= 0 or non-finite scalars
+  kStall = 7       // true residual stopped improving (mixed inner solves only)
 };
 
 // How a finisher completes a PCG step.
