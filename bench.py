@@ -3,7 +3,7 @@
 One step = one lp_unwrap_batch call over the uneven batch workload (256
 random-Gaussian maps, sides drawn from {128,256,384,512,768,1024}, noise
 sigma ~ U[0.1, 0.8] rad, p = 0, tau = 0.01, 10 outer iterations, DCT
-preconditioner, mixed precision with split-bf16 MFMA transforms), with every
+preconditioner, mixed precision with scaled-fp16 MFMA transforms), with every
 psi already resident in HBM when the timed region starts.
 
 Prints one JSON line (rank 0) with the metric, the roofline of the dominant
@@ -28,6 +28,34 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 PEAK_BF16_TFLOPS = 2500.0
 PEAK_FP16_TFLOPS = 2500.0
+# measured HBM traffic per launch (rocprofv3 FETCH_SIZE / WRITE_SIZE passes,
+# scaled by a plain copy), valid while the kernel sources hash as recorded
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "traffic_batch256_fp16.txt")
+CLASS_SOURCE = {"dct": "engine_dct.hip", "spmv": "engine_kernels.hip",
+                "update": "engine_kernels.hip"}
+
+
+def measured_traffic(cls, dct_mode, maps):
+    """Bytes per launch of kernel class `cls` from the committed counter summary,
+    or None when the summary is missing, was taken on another workload, or the
+    kernel's source has changed since."""
+    import hashlib
+    if cls not in CLASS_SOURCE or maps != 256 or not os.path.exists(TRAFFIC_PROFILE):
+        return None
+    fields = {}
+    for line in open(TRAFFIC_PROFILE):
+        parts = line.split()
+        if len(parts) == 3 and parts[0] in ("traffic_bytes_per_launch", "source_sha256"):
+            fields[(parts[0], parts[1])] = parts[2]
+        elif len(parts) == 2 and parts[0] == "dct_mode":
+            fields["dct_mode"] = parts[1]
+    src = CLASS_SOURCE[cls]
+    path = os.path.join(ROOT, "paper_2203_13675_amd", "csrc", src)
+    digest = hashlib.sha256(open(path, "rb").read()).hexdigest()
+    if fields.get(("source_sha256", src)) != digest or fields.get("dct_mode") != dct_mode:
+        return None
+    v = fields.get(("traffic_bytes_per_launch", cls))
+    return float(v) if v is not None else None
 
 
 def parse():
@@ -37,7 +65,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--maps", type=int, default=256)
     ap.add_argument("--outer", type=int, default=10)
-    ap.add_argument("--dct-mode", default="split_bf16")
+    ap.add_argument("--dct-mode", default="fp16_scaled")
     ap.add_argument("--fp64-compare", type=int, default=1,
                     help="also time the plain FP64 sequential loop once (0: skip)")
     ap.add_argument("--cpu-baseline", type=int, default=1)
@@ -113,18 +141,21 @@ def main():
     roofline = None
     if dom:
         name, kt = dom
-        per_launch_s = kt["ms"] / 1e3 / max(kt["launches"], 1)
+        launches = max(kt["launches"], 1)
+        per_launch_s = kt["ms"] / 1e3 / launches
+        traffic = measured_traffic(name, a.dct_mode, a.maps)
+        common = {"kernel": name, "traffic": traffic, "traffic_unit": "bytes per launch",
+                  "alg_bytes_per_launch": kt["bytes"] / launches,
+                  "alg_flops_per_launch": kt["flops"] / launches,
+                  "avg_launch_us": per_launch_s * 1e6, "launches": kt["launches"]}
         if kt["flops"] > 0 and name.startswith("dct"):
-            ach = kt["flops"] / max(kt["launches"], 1) / per_launch_s / 1e12
-            roofline = {"bound": "mfma", "kernel": name, "achieved": ach,
-                        "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
-                        "frac": ach / PEAK_BF16_TFLOPS, "traffic": None,
-                        "avg_launch_us": per_launch_s * 1e6, "launches": kt["launches"]}
+            ach = kt["flops"] / launches / per_launch_s / 1e12
+            roofline = {"bound": "mfma", "achieved": ach, "peak": PEAK_FP16_TFLOPS,
+                        "unit": "TFLOP/s", "frac": ach / PEAK_FP16_TFLOPS, **common}
         else:
-            ach = kt["bytes"] / max(kt["launches"], 1) / per_launch_s / 1e9
-            roofline = {"bound": "hbm", "kernel": name, "achieved": ach, "peak": PEAK_HBM_GBS,
-                        "unit": "GB/s", "frac": ach / PEAK_HBM_GBS, "traffic": None,
-                        "avg_launch_us": per_launch_s * 1e6, "launches": kt["launches"]}
+            ach = kt["bytes"] / launches / per_launch_s / 1e9
+            roofline = {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS,
+                        "unit": "GB/s", "frac": ach / PEAK_HBM_GBS, **common}
 
     out = {
         "metric": "Mpixel/s unwrapped at 1e-6 rel. residual; batched mixed-prec vs plain FP64",

@@ -448,6 +448,8 @@ struct Pcg {
       s.period = period[k];
       s.rule = rule;
       s.stall = sizeof(T) == 4 ? 1 : 0;  // refinement follows every mixed inner solve
+      const long long px = (long long)e.hdesc[set[k]].M * e.hdesc[set[k]].N;
+      s.chk_gap = std::min(px, std::max(period[k], 256LL));
       s.state = kRun;
     }
     if ((rc = write_states(ctx))) return rc;

@@ -70,7 +70,8 @@ struct MapState {
   double alpha, beta;
   double dq, rr, bb, rs;
   double thr_rr, thr_delta, tol2, eps2;
-  double rr_chk;               // last true residual above the bound (stagnation test)
+  double rr_chk;               // true residual at the last stagnation checkpoint
+  long long l_chk, chk_gap;    // its iteration; least iterations between compared checkpoints
   long long l, l_max, period, nfinish;
   int state, rule, replaced, stall;  // stall: 1 = stop when the true residual stagnates
   float amax[4];

@@ -250,36 +250,50 @@ __global__ void __launch_bounds__(256) k_e_dct_mfma(DArgs a) {
 //   inverse: half 0 = u (spectrum columns [0, h)), half 1 = v (columns
 //            [h, n)), combined at the end into outputs c and n-1-c.
 // Wave w computes rows 64 (w & 1) .. +63 of half w >> 1 as 4 x 4 MFMA tiles
-// of 16 x 16 (64 accumulator registers).  Each K step of 32 stages both
-// halves of A (128 x 32) and of the table slice (64 x 32) in LDS, converted
+// of 16 x 16 (64 accumulator registers).  Each K step of KS (32 for the bf16
+// split, 64 for fp16, whose operands take half the registers) stages both
+// halves of A (128 x KS) and of the table slice (64 x KS) in LDS, converted
 // once to bf16 hi/lo (or scaled fp16); the next step's global loads are in
-// flight while the MFMAs of the current one run.  LDS rows are 64 bytes
-// without padding; the 16-byte chunk q of row r sits at q ^ swz(r), which
-// keeps both the staging writes and the fragment reads free of bank conflicts.
+// flight while the MFMAs of the current one run, so a longer step keeps more
+// bytes in flight per block.  LDS rows are KS 16-bit values without padding;
+// the 16-byte chunk q of row r sits at q ^ swz(r), which keeps both the
+// staging writes and the fragment reads free of bank conflicts (rows of 4
+// chunks: 8 rows read in one LDS cycle land in 8 distinct bank quads; rows of
+// 8 chunks: likewise for 8 or 16 rows).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int swz(int r) { return ((r >> 1) ^ (r >> 2)) & 3; }
-// offset (16-bit elements) of element 8q + e of LDS row r
-__device__ __forceinline__ int lds_at(int r, int q) { return r * 32 + ((q ^ swz(r)) << 3); }
+template <int NC>
+__device__ __forceinline__ int swz(int r) {
+  return NC == 4 ? (((r >> 1) ^ (r >> 2)) & 3) : ((r ^ (r >> 3)) & 7);
+}
+// offset (16-bit elements) of element 8q + e of LDS row r (rows of NC chunks)
+template <int NC>
+__device__ __forceinline__ int lds_at(int r, int q) { return r * (8 * NC) + ((q ^ swz<NC>(r)) << 3); }
 
 typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
 
 template <int SPLIT, int INV>
 __global__ void __launch_bounds__(256, 2) k_e_dct_eo(DArgs a) {
   constexpr int NP = SPLIT ? 2 : 1;                // hi (+ lo) planes
-  constexpr int kA = 128 * 32, kB = 64 * 32;       // elements of one A / B half-plane
+  constexpr int KS = SPLIT ? 32 : 64;              // K step
+  constexpr int NC = KS / 8;                       // 16-byte chunks per LDS row
+  constexpr int kA = 128 * KS, kB = 64 * KS;       // elements of one A / B half-plane
   constexpr int kStage = NP * 2 * (kA + kB) * 2;   // bytes of staged operands
   constexpr int kXchg = 2 * 16 * 64 * 16;          // bytes of the inverse's v exchange
   constexpr int kSmem = kStage > kXchg ? kStage : kXchg;
+  constexpr int TPR = KS / 4;                      // X staging: threads per row (4 values each)
+  constexpr int XP = 128 * TPR / 256;              // X staging passes (rows xr + XP-stride)
+  constexpr int SEGS = 256 / NC;                   // table staging: segments per pass
+  constexpr int TP = NP * 2 * 64 / SEGS;           // table staging passes
   __shared__ __attribute__((aligned(16))) unsigned char smem[kSmem];
   __shared__ double red[4];
-  uint16_t* As = reinterpret_cast<uint16_t*>(smem);  // [plane][half][128 x 32]
-  uint16_t* Bs = As + NP * 2 * kA;                   // [plane][half][64 x 32]
+  uint16_t* As = reinterpret_cast<uint16_t*>(smem);  // [plane][half][128 x KS]
+  uint16_t* Bs = As + NP * 2 * kA;                   // [plane][half][64 x KS]
   const int nact = a.counts[a.cidx];
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const int wr = (w & 1) * 64, hf = w >> 1;
   const int lr = lane & 15, kq = lane >> 4;        // MFMA operand map: row lr, k chunk kq
-  const int xr = tid >> 3, xk = (tid & 7) * 4;      // X staging: rows xr + 32 p, k xk .. +3
-  const int bseg = tid >> 2, bq = tid & 3;          // table staging: segment, 16-byte chunk
+  const int xr = tid / TPR, xk = (tid % TPR) * 4;   // X staging: rows xr + (256/TPR) p, k xk .. +3
+  const int bseg = tid / NC, bq = tid % NC;         // table staging: segment, 16-byte chunk
   for (int t_ = blockIdx.x; t_ < nact; t_ += gridDim.x) {
     const int g = a.dact[t_];
     if (g < 0) continue;  // padding slot of the XCD-ordered list
@@ -299,18 +313,18 @@ __global__ void __launch_bounds__(256, 2) k_e_dct_eo(DArgs a) {
       inv_xs = 1.0f / xs;
     }
     // register staging of one K step
-    float4 sa[4], sb[4];
-    u16x8 sT[NP * 2];
+    float4 sa[XP], sb[XP];
+    u16x8 sT[TP];
     auto fetch = [&](int k0) {
 #pragma unroll
-      for (int p = 0; p < 4; ++p) {
-        const float* row = X + (size_t)(t.r0 + xr + 32 * p) * n;
+      for (int p = 0; p < XP; ++p) {
+        const float* row = X + (size_t)(t.r0 + xr + (256 / TPR) * p) * n;
         sa[p] = *reinterpret_cast<const float4*>(row + k0 + xk);
         sb[p] = *reinterpret_cast<const float4*>(row + (INV ? h + k0 + xk : n - 4 - k0 - xk));
       }
 #pragma unroll
-      for (int p = 0; p < NP * 2; ++p) {
-        const int s = p * 64 + bseg;                  // segment: ((half * NP) + plane) * 64 + row
+      for (int p = 0; p < TP; ++p) {
+        const int s = p * SEGS + bseg;                // segment: ((half * NP) + plane) * 64 + row
         const int half = s / (64 * NP), plane = (s / 64) % NP, row = s & 63;
         const uint16_t* T = plane ? T1 : T0;
         const uint16_t* src = INV ? T + (size_t)(c0 + row) * n + (half ? h : 0) + k0 + 8 * bq
@@ -320,8 +334,8 @@ __global__ void __launch_bounds__(256, 2) k_e_dct_eo(DArgs a) {
     };
     auto stash = [&]() {
 #pragma unroll
-      for (int p = 0; p < 4; ++p) {
-        const int r = xr + 32 * p;
+      for (int p = 0; p < XP; ++p) {
+        const int r = xr + (256 / TPR) * p;
         const float av[4] = {sa[p].x, sa[p].y, sa[p].z, sa[p].w};
         // forward: the b part is x mirrored, x[n-1-k] for k = k0 + xk .. +3
         const float bv[4] = {INV ? sb[p].x : sb[p].w, INV ? sb[p].y : sb[p].z,
@@ -342,7 +356,7 @@ __global__ void __launch_bounds__(256, 2) k_e_dct_eo(DArgs a) {
             hv[1][e] = __builtin_bit_cast(uint16_t, (_Float16)(v1 * xs));
           }
         }
-        const int o = lds_at(r, xk >> 3) + (xk & 4);
+        const int o = lds_at<NC>(r, xk >> 3) + (xk & 4);
 #pragma unroll
         for (int half = 0; half < 2; ++half) {
           *reinterpret_cast<u16x4*>(As + (0 * 2 + half) * kA + o) = hv[half];
@@ -350,10 +364,10 @@ __global__ void __launch_bounds__(256, 2) k_e_dct_eo(DArgs a) {
         }
       }
 #pragma unroll
-      for (int p = 0; p < NP * 2; ++p) {
-        const int s = p * 64 + bseg;
+      for (int p = 0; p < TP; ++p) {
+        const int s = p * SEGS + bseg;
         const int half = s / (64 * NP), plane = (s / 64) % NP, row = s & 63;
-        *reinterpret_cast<u16x8*>(Bs + (plane * 2 + half) * kB + lds_at(row, bq)) = sT[p];
+        *reinterpret_cast<u16x8*>(Bs + (plane * 2 + half) * kB + lds_at<NC>(row, bq)) = sT[p];
       }
     };
     f32x4 acc[4][4];
@@ -361,28 +375,31 @@ __global__ void __launch_bounds__(256, 2) k_e_dct_eo(DArgs a) {
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const int nsteps = h / 32;
+    const int nsteps = h / KS;
     fetch(0);
     for (int s = 0; s < nsteps; ++s) {
       __syncthreads();  // readers of the previous step (or tile) are done
       stash();
       __syncthreads();
-      if (s + 1 < nsteps) fetch((s + 1) * 32);
+      if (s + 1 < nsteps) fetch((s + 1) * KS);
       const uint16_t* Ah = As + (0 * 2 + hf) * kA;
       const uint16_t* Al = As + (1 * 2 + hf) * kA;
       const uint16_t* Bh = Bs + (0 * 2 + hf) * kB;
       const uint16_t* Bl = Bs + (1 * 2 + hf) * kB;
+#pragma unroll
+      for (int ks = 0; ks < KS / 32; ++ks) {
+      const int q = 4 * ks + kq;
       u16x8 bh[4], bl[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        bh[j] = *reinterpret_cast<const u16x8*>(Bh + lds_at(16 * j + lr, kq));
-        if (SPLIT) bl[j] = *reinterpret_cast<const u16x8*>(Bl + lds_at(16 * j + lr, kq));
+        bh[j] = *reinterpret_cast<const u16x8*>(Bh + lds_at<NC>(16 * j + lr, q));
+        if (SPLIT) bl[j] = *reinterpret_cast<const u16x8*>(Bl + lds_at<NC>(16 * j + lr, q));
       }
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const u16x8 ah = *reinterpret_cast<const u16x8*>(Ah + lds_at(wr + 16 * i + lr, kq));
+        const u16x8 ah = *reinterpret_cast<const u16x8*>(Ah + lds_at<NC>(wr + 16 * i + lr, q));
         u16x8 al;
-        if (SPLIT) al = *reinterpret_cast<const u16x8*>(Al + lds_at(wr + 16 * i + lr, kq));
+        if (SPLIT) al = *reinterpret_cast<const u16x8*>(Al + lds_at<NC>(wr + 16 * i + lr, q));
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           if (SPLIT) {
@@ -398,6 +415,7 @@ __global__ void __launch_bounds__(256, 2) k_e_dct_eo(DArgs a) {
           }
         }
       }
+      }  // ks
     }
     // epilogue: lane holds D[row 4*(lane/16) + e][col lane mod 16] of each 16x16 tile
     const MapDesc& d = a.desc[t.m];

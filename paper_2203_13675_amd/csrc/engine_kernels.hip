@@ -28,12 +28,39 @@ struct R2 {
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 
+// Lane moves on the VALU instead of the LDS crossbar: DPP whole-wave shifts
+// by one lane (wave_shr:1 = 0x138: lane l receives lane l-1; wave_shl:1 =
+// 0x130: lane l receives lane l+1; the lane with no source receives 0 and is
+// overwritten by the caller) and readlane broadcasts.
+template <int CTRL>
+__device__ __forceinline__ int dpp32(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, true);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v) {
+  return __builtin_bit_cast(float, dpp32<CTRL>(__builtin_bit_cast(int, v)));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = dpp32<CTRL>((int)(b & 0xffffffffLL)), hi = dpp32<CTRL>((int)(b >> 32));
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ float bcast(float v, int src) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), src));
+}
+__device__ __forceinline__ double bcast(double v, int src) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), src);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
 template <typename T>
-__device__ __forceinline__ T shup(T v) { return __shfl_up(v, 1, 64); }
+__device__ __forceinline__ T shup(T v) { return dpp_move<0x138>(v); }
 template <typename T>
-__device__ __forceinline__ T shdn(T v) { return __shfl_down(v, 1, 64); }
+__device__ __forceinline__ T shdn(T v) { return dpp_move<0x130>(v); }
 template <typename T>
-__device__ __forceinline__ T shfrom(T v, int src) { return __shfl(v, src, 64); }
+__device__ __forceinline__ T shfrom(T v, int src) { return bcast(v, src); }
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -583,15 +610,26 @@ __device__ inline void map_finish(MapState& s, int mode, double rs) {
   s.state = st;
 }
 
-// Stagnation of a mixed-precision inner solve: a true residual (a periodic
-// replacement or a failed confirmation) above the bound that is not at least
-// 10 % (in norm) below the previous one.  The FP32 iterate has then reached
-// what its precision can resolve; the FP64 refinement around the solve takes
-// over from the best iterate.
+// Stagnation of a mixed-precision inner solve.  Checkpoints are the true
+// residuals the iteration forms anyway (periodic replacements and failed
+// confirmations).  Two checkpoints at least chk_gap iterations apart are
+// compared (chk_gap = min(MN, max(period, 256)): in exact arithmetic CG ends
+// within MN iterations, and over shorter spans the residual norm of CG need
+// not decrease); if the later one is still above the bound and not at least
+// 10 % (in norm) below the earlier one, the FP32 iterate has reached what its
+// precision can resolve and the solve stops; the FP64 refinement around it
+// continues from its iterate.
 __device__ inline bool stagnated(MapState& s, double rr_true) {
   if (!s.stall || s.rule != LPU_STOP_RELRES || rr_true <= s.thr_rr) return false;
-  const bool stuck = s.rr_chk > 0.0 && rr_true >= 0.81 * s.rr_chk;
+  if (s.rr_chk <= 0.0) {
+    s.rr_chk = rr_true;
+    s.l_chk = s.l;
+    return false;
+  }
+  if (s.l - s.l_chk < s.chk_gap) return false;
+  const bool stuck = rr_true >= 0.81 * s.rr_chk;
   s.rr_chk = rr_true;
+  s.l_chk = s.l;
   return stuck;
 }
 
@@ -661,7 +699,7 @@ __global__ void __launch_bounds__(256) k_e_finish(const MapDesc* __restrict__ de
       s.replaced = replace ? 1 : 0;
       if (replace && stagnated(s, v[0])) {
         s.delta_old = s.delta_new;
-        s.l += 1;
+        s.l += 1;  // the iterate of this update is the one returned
         s.state = kStall;
       } else if (s.rule == LPU_STOP_RELRES && !replace && v[0] <= s.thr_rr) {
         s.delta_old = s.delta_new;
