@@ -13,6 +13,8 @@
 //               - V_{i,j} x_{i+1,j} - V_{i-1,j} x_{i-1,j},
 // out-of-grid terms zero (U is 0 on the last column, V on the last row).
 
+#include <type_traits>
+
 #include "lpu_internal.h"
 #include "lpu_device.h"
 
@@ -24,6 +26,11 @@ namespace lpu {
 template <typename T>
 struct R2 {
   T a, b;  // columns j0 + lane, j0 + 64 + lane
+};
+
+template <typename T>
+struct R3 {
+  T s, w, d;  // raw loads of one operand element (see the field loaders)
 };
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
@@ -103,9 +110,21 @@ __device__ __forceinline__ void neighbours(const R2<T>& v, T halo, R2<T>& w, R2<
   e.b = l < 63 ? dn_b : h63;   // column j0 + 128 for lane 63
 }
 
+// In-grid index of (i, j) clamped to the grid, and whether (i, j) is inside.
+// Loads through a clamped index always execute (no lane-divergent branch
+// around them), so the compiler can issue the loads of several rows at once;
+// the value is then replaced by zero where (i, j) is outside.
+__device__ __forceinline__ size_t clamp_at(int i, int j, int M, int N, bool& ok) {
+  ok = (unsigned)i < (unsigned)M && (unsigned)j < (unsigned)N;
+  const int ic = min(max(i, 0), M - 1), jc = min(max(j, 0), N - 1);
+  return (size_t)ic * N + jc;
+}
+
 template <typename T>
 __device__ __forceinline__ T ldz(const T* __restrict__ a, int i, int j, int M, int N) {
-  return (i >= 0 && i < M && j >= 0 && j < N) ? a[(size_t)i * N + j] : T(0);
+  bool ok;
+  const T v = a[clamp_at(i, j, M, N, ok)];
+  return ok ? v : T(0);
 }
 
 template <typename T>
@@ -128,41 +147,71 @@ __device__ __forceinline__ T stencil5(T uw, T uc, T vn, T vc, T xc, T xw, T xe, 
   return (uw + uc + vn + vc) * xc - uc * xe - uw * xw - vc * xs - vn * xn;
 }
 
-// March the tile: for every interior pixel call epi(i, j, x_ij, (A x)_ij),
-// where the operand x is given by field(i, j) (zero outside the grid).
-template <int TH, typename T, typename F, typename E>
+// March the tile: for every interior pixel call epi(i, j, x_ij, (A x)_ij).
+// The operand x is formed as make(load(i, j)): load issues the raw loads of
+// one element (zero outside the grid, through a clamped index), make combines
+// them.  Loads run two rows ahead of the arithmetic (operand row i + 2, U and
+// V row i + 1 while row i is computed) and their values are first combined in
+// the next step, so a row's loads are in flight while the previous row is
+// computed and stored (vector loads and stores share one counter on this
+// architecture; a value used in the step that loads it would make the wave
+// wait for everything issued before).
+template <int TH, bool FULL, typename T, typename Ld, typename Mk, typename E>
 __device__ __forceinline__ void march_stencil(const TilePos& tp, const T* __restrict__ U,
-                                              const T* __restrict__ V, F field, E epi) {
+                                              const T* __restrict__ V, Ld load, Mk make, E epi) {
   const int M = tp.M, N = tp.N, i0 = tp.i0, j0 = tp.j0, l = lane_id();
-  const int hj = halo_col(j0);
+  const int hj = halo_col(j0), uj = l == 0 ? j0 - 1 : -1;
   const int ca = j0 + l, cb = j0 + 64 + l;
-  auto frow = [&](int i) {
-    R2<T> v;
-    v.a = field(i, ca);
-    v.b = field(i, cb);
-    return v;
+  using Raw = decltype(load(0, 0));
+  struct Row {
+    Raw a, b, h;  // columns ca, cb and this lane's halo column
   };
-  R2<T> xm = frow(i0 - 1), xc = frow(i0);
-  T xh = field(i0, hj);
-  R2<T> vn = ldrow(V, i0 - 1, j0, M, N);
+  auto lrow = [&](int i) {
+    Row r;
+    r.a = load(i, ca);
+    r.b = load(i, cb);
+    r.h = load(i, hj);
+    return r;
+  };
+  R2<T> xm, xc;
+  {
+    const Row rm = lrow(i0 - 1), rc = lrow(i0);
+    xm.a = make(rm.a);
+    xm.b = make(rm.b);
+    xc.a = make(rc.a);
+    xc.b = make(rc.b);
+  }
+  T xh = make(lrow(i0).h);
+  Row rp = lrow(i0 + 1);
+  R2<T> vn = ldrow(V, i0 - 1, j0, M, N), vc = ldrow(V, i0, j0, M, N);
+  R2<T> uc = ldrow(U, i0, j0, M, N);
+  T uh = ldz(U, i0, uj, M, N);
   auto step = [&](int k) {
     const int i = i0 + k;
-    const R2<T> xp = frow(i + 1);
-    const T xph = field(i + 1, hj);
-    const R2<T> uc = ldrow(U, i, j0, M, N);
-    const T uh = (l == 0) ? ldz(U, i, j0 - 1, M, N) : T(0);
-    const R2<T> vc = ldrow(V, i, j0, M, N);
+    // next rows' loads first
+    const Row rpp = lrow(i + 2);
+    const R2<T> un = ldrow(U, i + 1, j0, M, N);
+    const T unh = ldz(U, i + 1, uj, M, N);
+    const R2<T> vnx = ldrow(V, i + 1, j0, M, N);
+    R2<T> xp;
+    xp.a = make(rp.a);
+    xp.b = make(rp.b);
+    const T xph = make(rp.h);
     R2<T> xw, xe, uw, ue;
     neighbours(xc, xh, xw, xe);
     neighbours(uc, uh, uw, ue);
-    if (ca < N)
+    if (FULL || ca < N)
       epi(i, ca, xc.a, stencil5<T>(uw.a, uc.a, vn.a, vc.a, xc.a, xw.a, xe.a, xm.a, xp.a));
-    if (cb < N)
+    if (FULL || cb < N)
       epi(i, cb, xc.b, stencil5<T>(uw.b, uc.b, vn.b, vc.b, xc.b, xw.b, xe.b, xm.b, xp.b));
     xm = xc;
     xc = xp;
     xh = xph;
+    rp = rpp;
     vn = vc;
+    vc = vnx;
+    uc = un;
+    uh = unh;
   };
   // TH > 0: compile-time tile height, unrolled (the lane shuffles inside keep
   // the compiler from unrolling a loop of run-time length); TH == 0: tp.rows
@@ -176,6 +225,16 @@ __device__ __forceinline__ void march_stencil(const TilePos& tp, const T* __rest
     const int kend = min(tp.rows, M - i0);
     for (int k = 0; k < kend; ++k) step(k);
   }
+}
+
+// Tiles that lie wholly inside the map's columns (every map side a multiple
+// of 128 gives only such tiles) take a copy of the march without per-lane
+// column guards, so no store or load sits behind a lane-divergent branch.
+template <int TH, typename T, typename Ld, typename Mk, typename E>
+__device__ __forceinline__ void march_tile(const TilePos& tp, const T* __restrict__ U,
+                                           const T* __restrict__ V, Ld load, Mk make, E epi) {
+  if (tp.j0 + kTW <= tp.N) march_stencil<TH, true, T>(tp, U, V, load, make, epi);
+  else march_stencil<TH, false, T>(tp, U, V, load, make, epi);
 }
 
 // Elementwise walk over the tile's pixels.
@@ -431,7 +490,8 @@ __global__ void __launch_bounds__(64) k_e_resid(EArgs A) {
     T* d0 = vec<T>(A.d0, tp.off);
     const int M = tp.M, N = tp.N;
     double srr = 0.0, srs = 0.0, sbb = 0.0;
-    march_stencil<0, T>(tp, U, V, [&](int i, int j) { return ldz(x, i, j, M, N); },
+    march_tile<0, T>(tp, U, V, [&](int i, int j) { return ldz(x, i, j, M, N); },
+                     [](T v) { return v; },
                      [&](int i, int j, T, T ax) {
                        const size_t p = (size_t)i * N + j;
                        const T bv = b[p];
@@ -473,14 +533,20 @@ __global__ void __launch_bounds__(64) k_e_spmv(EArgs A) {
     T* q = vec<T>(A.q, tp.off);
     const int M = tp.M, N = tp.N;
     double sdq = 0.0;
-    march_stencil<TH, T>(
+    march_tile<TH, T>(
         tp, U, V,
         [&](int i, int j) {
-          if (i < 0 || i >= M || j < 0 || j >= N) return T(0);
-          const size_t p = (size_t)i * N + j;
-          const T sv = PC == kPcJacobi ? src[p] * aux[p] : src[p];
-          return sv + beta * dold[p];
+          bool ok;
+          const size_t p = clamp_at(i, j, M, N, ok);
+          // unconditional loads through the clamped index, zeroed outside the grid
+          const T s0 = src[p], d0 = dold[p];
+          R3<T> v;  // s (or r), inverse diagonal, d_old
+          v.s = ok ? s0 : T(0);
+          v.w = PC == kPcJacobi ? aux[p] : T(1);
+          v.d = ok ? d0 : T(0);
+          return v;
         },
+        [&](const R3<T>& v) { return (PC == kPcJacobi ? v.s * v.w : v.s) + beta * v.d; },
         [&](int i, int j, T dv, T qv) {
           const size_t p = (size_t)i * N + j;
           dnew[p] = dv;
@@ -516,13 +582,19 @@ __global__ void __launch_bounds__(64) k_e_update(EArgs A) {
     const int M = tp.M, N = tp.N;
     double srr = 0.0, srs = 0.0;
     if (replace) {
-      march_stencil<TH, T>(
+      march_tile<TH, T>(
           tp, U, V,
           [&](int i, int j) {
-            if (i < 0 || i >= M || j < 0 || j >= N) return T(0);
-            const size_t p = (size_t)i * N + j;
-            return xold[p] + alpha * d[p];
+            bool ok;
+            const size_t p = clamp_at(i, j, M, N, ok);
+            const T x0 = xold[p], d0 = d[p];
+            R3<T> v;  // x_old, unused, d; zeroed outside the grid
+            v.s = ok ? x0 : T(0);
+            v.w = T(1);
+            v.d = ok ? d0 : T(0);
+            return v;
           },
+          [&](const R3<T>& v) { return v.s + alpha * v.d; },
           [&](int i, int j, T xv, T ax) {
             const size_t p = (size_t)i * N + j;
             const T rv = b[p] - ax;
@@ -533,15 +605,50 @@ __global__ void __launch_bounds__(64) k_e_update(EArgs A) {
             srs += (double)rv * (double)sv;
           });
     } else {
-      march_points(tp, [&](int i, int j) {
-        const size_t p = (size_t)i * N + j;
-        xnew[p] = xold[p] + alpha * d[p];
-        const T rv = r[p] - alpha * q[p];
-        r[p] = rv;
-        const T sv = PC == kPcJacobi ? rv * aux[p] : rv;
-        srr += (double)rv * (double)rv;
-        srs += (double)rv * (double)sv;
-      });
+      // elementwise; loads through a clamped column (always executed, so the
+      // loads of several rows can be in flight), stores only on the map
+      const int l = lane_id();
+      const int ja = min(tp.j0 + l, N - 1), jb = min(tp.j0 + 64 + l, N - 1);
+      const bool oka = tp.j0 + l < N, okb = tp.j0 + 64 + l < N;
+      const int kend = min(TH > 0 ? TH : tp.rows, M - tp.i0);
+      // four rows at a time: all loads of the group (through a clamped row)
+      // are issued before its first store, so 32 loads per wave are in flight
+      auto walk = [&](auto full_tag) {
+        constexpr bool FULL = decltype(full_tag)::value;
+        constexpr int G = 4;
+        for (int k0 = 0; k0 < kend; k0 += G) {
+          T xv[G][2], dv[G][2], rv[G][2], qv[G][2], wv[G][2];
+#pragma unroll
+          for (int c = 0; c < G; ++c) {
+            const size_t row = (size_t)min(tp.i0 + k0 + c, M - 1) * N;
+            const size_t pa = row + ja, pb = row + jb;
+            xv[c][0] = xold[pa], xv[c][1] = xold[pb];
+            dv[c][0] = d[pa], dv[c][1] = d[pb];
+            rv[c][0] = r[pa], rv[c][1] = r[pb];
+            qv[c][0] = q[pa], qv[c][1] = q[pb];
+            wv[c][0] = PC == kPcJacobi ? aux[pa] : T(1);
+            wv[c][1] = PC == kPcJacobi ? aux[pb] : T(1);
+          }
+#pragma unroll
+          for (int c = 0; c < G; ++c) {
+            if (k0 + c >= kend) break;  // uniform over the wave
+            const size_t row = (size_t)(tp.i0 + k0 + c) * N;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+              if (!FULL && !(h ? okb : oka)) continue;
+              const size_t p = row + (h ? jb : ja);
+              const T rn = rv[c][h] - alpha * qv[c][h];
+              xnew[p] = xv[c][h] + alpha * dv[c][h];
+              r[p] = rn;
+              const T sv = PC == kPcJacobi ? rn * wv[c][h] : rn;
+              srr += (double)rn * (double)rn;
+              srs += (double)rn * (double)sv;
+            }
+          }
+        }
+      };
+      if (tp.j0 + kTW <= N) walk(std::true_type());
+      else walk(std::false_type());
     }
     srr = wave_sum(srr);
     srs = wave_sum(srs);
@@ -563,7 +670,8 @@ __global__ void __launch_bounds__(64) k_e_apply(EArgs A) {
     const T* x = cvec<T>(A.s, tp.off);
     T* y = vec<T>(A.q, tp.off);
     const int M = tp.M, N = tp.N;
-    march_stencil<0, T>(tp, U, V, [&](int i, int j) { return ldz(x, i, j, M, N); },
+    march_tile<0, T>(tp, U, V, [&](int i, int j) { return ldz(x, i, j, M, N); },
+                     [](T v) { return v; },
                      [&](int i, int j, T, T ax) { y[(size_t)i * N + j] = ax; });
   }
 }
