@@ -578,8 +578,11 @@ static int run_maps(lp_unwrap_ctx* ctx, int n, const lpu_map* maps, double p, do
         const double prod = (kd == 2 || kd == 4) ? 3.0 : 1.0;
         const double half = kd >= 4 ? 0.5 : 1.0;
         const double tab = kd == 0 ? 8.0 : (kd == 1 ? 4.0 : ((kd == 2 || kd == 4) ? 4.0 : 2.0));
-        const double bytes = 2.0 * (2.0 * px * el + half * Nn * Nn * tab) +
-                             2.0 * (2.0 * px * el + half * Mm * Mm * tab) + px * el;
+        // X in, Out out per stage (the scaled-fp16 even/odd path keeps the
+        // three intermediates in 2 bytes), the tables, r in the last stage
+        const double io = kd == 5 ? px * (4.0 + 2.0 + 2.0 + 2.0 + 2.0 + 2.0 + 2.0 + 4.0)
+                                  : 8.0 * px * el;
+        const double bytes = io + 2.0 * half * Nn * Nn * tab + 2.0 * half * Mm * Mm * tab + px * el;
         kt.credit(LPU_KC_DCT, 4 * s.nfinish, s.nfinish * bytes,
                   s.nfinish * 4.0 * px * (Mm + Nn) * prod * half);
       } else if (!pcg.pointwise()) {

@@ -271,7 +271,7 @@ __device__ __forceinline__ int lds_at(int r, int q) { return r * (8 * NC) + ((q 
 
 typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
 
-template <int SPLIT, int INV>
+template <int SPLIT, int INV, int IN16, int OUT16>
 __global__ void __launch_bounds__(256, 2) k_e_dct_eo(DArgs a) {
   constexpr int NP = SPLIT ? 2 : 1;                // hi (+ lo) planes
   constexpr int KS = SPLIT ? 32 : 64;              // K step
@@ -280,7 +280,8 @@ __global__ void __launch_bounds__(256, 2) k_e_dct_eo(DArgs a) {
   constexpr int kStage = NP * 2 * (kA + kB) * 2;   // bytes of staged operands
   constexpr int kXchg = 2 * 16 * 64 * 16;          // bytes of the inverse's v exchange
   constexpr int kSmem = kStage > kXchg ? kStage : kXchg;
-  constexpr int TPR = KS / 4;                      // X staging: threads per row (4 values each)
+  constexpr int VPT = IN16 ? 8 : 4;                // X staging: values per thread and load
+  constexpr int TPR = KS / VPT;                    // X staging: threads per row
   constexpr int XP = 128 * TPR / 256;              // X staging passes (rows xr + XP-stride)
   constexpr int SEGS = 256 / NC;                   // table staging: segments per pass
   constexpr int TP = NP * 2 * 64 / SEGS;           // table staging passes
@@ -292,7 +293,8 @@ __global__ void __launch_bounds__(256, 2) k_e_dct_eo(DArgs a) {
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const int wr = (w & 1) * 64, hf = w >> 1;
   const int lr = lane & 15, kq = lane >> 4;        // MFMA operand map: row lr, k chunk kq
-  const int xr = tid / TPR, xk = (tid % TPR) * 4;   // X staging: rows xr + (256/TPR) p, k xk .. +3
+  const int xr = tid / TPR, xk = (tid % TPR) * VPT;  // X staging: rows xr + (256/TPR) p, k xk ..
+  static_assert(!(SPLIT && (IN16 || OUT16)), "the bf16 split keeps FP32 intermediates");
   const int bseg = tid / NC, bq = tid % NC;         // table staging: segment, 16-byte chunk
   for (int t_ = blockIdx.x; t_ < nact; t_ += gridDim.x) {
     const int g = a.dact[t_];
@@ -301,26 +303,43 @@ __global__ void __launch_bounds__(256, 2) k_e_dct_eo(DArgs a) {
     if (!t.ok) continue;  // uniform over the block
     const int R = t.R, n = t.K, h = n >> 1, c0 = t.c0;
     const float* X = reinterpret_cast<const float*>(a.X) + t.off;
+    const uint16_t* X16 = reinterpret_cast<const uint16_t*>(a.X) + t.off;
     float* Out = reinterpret_cast<float*>(a.Out) + t.off;
+    uint16_t* Out16 = reinterpret_cast<uint16_t*>(a.Out) + t.off;
     const uint16_t* T0 = INV ? (SPLIT ? t.tab->eot_hi : t.tab->eot_h) : (SPLIT ? t.tab->eo_hi : t.tab->eo_h);
     const uint16_t* T1 = INV ? t.tab->eot_lo : t.tab->eo_lo;
     MapState& st = a.ms[t.m];
-    float xs = 1.0f, inv_xs = 1.0f;
+    float xs = 1.0f, inv_xs = 1.0f, os = 1.0f;
     if (!SPLIT) {
-      float amax = a.stage == 0 ? (float)sqrt(st.rr) * 1.0000001f : st.amax[a.stage];
-      if (!INV) amax *= 2.0f;  // x_a +- x_b
-      xs = fp16_scale(amax);
+      // Scaled fp16: power-of-two scales from bounds that hold before any
+      // value exists.  The transforms are orthonormal, so every stage output
+      // is bounded by the Frobenius norm of r (first forward stage; twice
+      // that after the even/odd fold) or of S ./ Lambda <= ||r|| / lambda_min
+      // (second forward stage and the first inverse stage).
+      const MapDesc& dm = a.desc[t.m];
+      const float nr = (float)sqrt(st.rr) * 1.0000001f;
+      const float lmin = (float)fmin(dm.tabM->lam[1], dm.tabN->lam[1]);
+      const float b01 = 2.0f * nr, b23 = nr / lmin * 1.0000001f;
+      xs = fp16_scale(a.stage <= 1 ? b01 : b23);
       inv_xs = 1.0f / xs;
+      os = fp16_scale(a.stage == 0 ? b01 : b23);
     }
     // register staging of one K step
-    float4 sa[XP], sb[XP];
+    float4 sa[IN16 ? 1 : XP], sb[IN16 ? 1 : XP];
+    u16x8 ha[IN16 ? XP : 1], hb[IN16 ? XP : 1];
     u16x8 sT[TP];
     auto fetch = [&](int k0) {
 #pragma unroll
       for (int p = 0; p < XP; ++p) {
-        const float* row = X + (size_t)(t.r0 + xr + (256 / TPR) * p) * n;
-        sa[p] = *reinterpret_cast<const float4*>(row + k0 + xk);
-        sb[p] = *reinterpret_cast<const float4*>(row + (INV ? h + k0 + xk : n - 4 - k0 - xk));
+        const size_t ro = (size_t)(t.r0 + xr + (256 / TPR) * p) * n;
+        const int ka = k0 + xk, kb = INV ? h + k0 + xk : n - VPT - k0 - xk;
+        if (IN16) {
+          ha[p] = *reinterpret_cast<const u16x8*>(X16 + ro + ka);
+          hb[p] = *reinterpret_cast<const u16x8*>(X16 + ro + kb);
+        } else {
+          sa[p] = *reinterpret_cast<const float4*>(X + ro + ka);
+          sb[p] = *reinterpret_cast<const float4*>(X + ro + kb);
+        }
       }
 #pragma unroll
       for (int p = 0; p < TP; ++p) {
@@ -333,6 +352,29 @@ __global__ void __launch_bounds__(256, 2) k_e_dct_eo(DArgs a) {
       }
     };
     auto stash = [&]() {
+      if constexpr (IN16) {
+        // fp16 input already carries the stage's scale: the inverse copies
+        // it, the forward folds x_a +- x_b in FP32 and rounds once more
+#pragma unroll
+        for (int p = 0; p < XP; ++p) {
+          const int r = xr + (256 / TPR) * p;
+          u16x8 v0 = ha[p], v1 = hb[p];
+          if (!INV) {
+            // whole-vector form: x_b reversed (it holds x[n-1-k] from the top),
+            // sum and difference in FP32, one rounding back to fp16
+            const f16x8 fa = __builtin_bit_cast(f16x8, ha[p]);
+            const f16x8 fbr = __builtin_bit_cast(f16x8, hb[p]);
+            const f16x8 fb = __builtin_shufflevector(fbr, fbr, 7, 6, 5, 4, 3, 2, 1, 0);
+            const f32x8 a32 = __builtin_convertvector(fa, f32x8);
+            const f32x8 b32 = __builtin_convertvector(fb, f32x8);
+            v0 = __builtin_bit_cast(u16x8, __builtin_convertvector(a32 + b32, f16x8));
+            v1 = __builtin_bit_cast(u16x8, __builtin_convertvector(a32 - b32, f16x8));
+          }
+          const int o = lds_at<NC>(r, xk >> 3);
+          *reinterpret_cast<u16x8*>(As + 0 * kA + o) = v0;
+          *reinterpret_cast<u16x8*>(As + 1 * kA + o) = v1;
+        }
+      } else {
 #pragma unroll
       for (int p = 0; p < XP; ++p) {
         const int r = xr + (256 / TPR) * p;
@@ -362,6 +404,7 @@ __global__ void __launch_bounds__(256, 2) k_e_dct_eo(DArgs a) {
           *reinterpret_cast<u16x4*>(As + (0 * 2 + half) * kA + o) = hv[half];
           if (SPLIT) *reinterpret_cast<u16x4*>(As + (1 * 2 + half) * kA + o) = lv[half];
         }
+      }
       }
 #pragma unroll
       for (int p = 0; p < TP; ++p) {
@@ -422,7 +465,6 @@ __global__ void __launch_bounds__(256, 2) k_e_dct_eo(DArgs a) {
     const float* rv = reinterpret_cast<const float*>(a.rvec) + t.off;
     const unsigned char* iso = (a.iso && d.use_iso) ? a.iso + t.off : nullptr;
     double part = 0.0;
-    float vmax = 0.0f;
     auto emit = [&](int c, int rb, const float (&y)[4]) {
       float v[4];
 #pragma unroll
@@ -438,9 +480,15 @@ __global__ void __launch_bounds__(256, 2) k_e_dct_eo(DArgs a) {
           part += (double)rv[o] * (double)yy;
         }
         v[e] = yy;
-        vmax = fmaxf(vmax, fabsf(yy));
       }
-      *reinterpret_cast<float4*>(Out + (size_t)c * R + rb) = make_float4(v[0], v[1], v[2], v[3]);
+      if (OUT16) {
+        u16x4 hv;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) hv[e] = __builtin_bit_cast(uint16_t, (_Float16)(v[e] * os));
+        *reinterpret_cast<u16x4*>(Out16 + (size_t)c * R + rb) = hv;
+      } else {
+        *reinterpret_cast<float4*>(Out + (size_t)c * R + rb) = make_float4(v[0], v[1], v[2], v[3]);
+      }
     };
     if (!INV) {
 #pragma unroll
@@ -481,12 +529,6 @@ __global__ void __launch_bounds__(256, 2) k_e_dct_eo(DArgs a) {
           }
         }
       }
-    }
-    if (!SPLIT && a.stage < 3) {
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) vmax = fmaxf(vmax, __shfl_down(vmax, off, 64));
-      if (lane == 0)
-        atomicMax(reinterpret_cast<unsigned int*>(&st.amax[a.stage + 1]), __float_as_uint(vmax));
     }
     if (a.stage == 3) {
       double vv[1] = {part};
@@ -612,10 +654,14 @@ void e_dct_stage(hipStream_t st, const Engine& e, int ndtiles, int stage, int ex
   else if (kind == 1) hipLaunchKernelGGL(k_e_dct_fma<float>, dim3(grid), dim3(256), 0, st, a);
   else if (kind == 2) hipLaunchKernelGGL(k_e_dct_mfma<1>, dim3(grid), dim3(256), 0, st, a);
   else if (kind == 3) hipLaunchKernelGGL(k_e_dct_mfma<0>, dim3(grid), dim3(256), 0, st, a);
-  else if (kind == 4 && stage < 2) hipLaunchKernelGGL((k_e_dct_eo<1, 0>), dim3(grid), dim3(256), 0, st, a);
-  else if (kind == 4) hipLaunchKernelGGL((k_e_dct_eo<1, 1>), dim3(grid), dim3(256), 0, st, a);
-  else if (stage < 2) hipLaunchKernelGGL((k_e_dct_eo<0, 0>), dim3(grid), dim3(256), 0, st, a);
-  else hipLaunchKernelGGL((k_e_dct_eo<0, 1>), dim3(grid), dim3(256), 0, st, a);
+  // scaled fp16 even/odd: intermediates between the stages are stored as
+  // scaled fp16 (first stage reads FP32 r, last stage writes FP32 s)
+  else if (kind == 4 && stage < 2) hipLaunchKernelGGL((k_e_dct_eo<1, 0, 0, 0>), dim3(grid), dim3(256), 0, st, a);
+  else if (kind == 4) hipLaunchKernelGGL((k_e_dct_eo<1, 1, 0, 0>), dim3(grid), dim3(256), 0, st, a);
+  else if (stage == 0) hipLaunchKernelGGL((k_e_dct_eo<0, 0, 0, 1>), dim3(grid), dim3(256), 0, st, a);
+  else if (stage == 1) hipLaunchKernelGGL((k_e_dct_eo<0, 0, 1, 1>), dim3(grid), dim3(256), 0, st, a);
+  else if (stage == 2) hipLaunchKernelGGL((k_e_dct_eo<0, 1, 1, 1>), dim3(grid), dim3(256), 0, st, a);
+  else hipLaunchKernelGGL((k_e_dct_eo<0, 1, 1, 0>), dim3(grid), dim3(256), 0, st, a);
 }
 
 // ---------------------------------------------------------------------------
