@@ -862,7 +862,11 @@ int step_precond(lp_unwrap_ctx* ctx, int M, int N, int pc, int dct_mode, double 
     const int kind = dct_kind_for(e, sizeof(T) == 4, dct_mode);
     const void* in[4] = {e.r, e.t1, e.t2, e.t1};
     void* out[4] = {e.t1, e.t2, e.t1, e.s};
-    for (int k = 0; k < 4; ++k) e_dct_stage(st, e, e.total_dtiles, k, kRun, kind, in[k], out[k], e.r);
+    for (int k = 0; k < 4; ++k) {
+      const int ev = ctx->kt.begin(LPU_KC_DCT, st);
+      e_dct_stage(st, e, e.total_dtiles, k, kRun, kind, in[k], out[k], e.r);
+      ctx->kt.end(ev, LPU_KC_DCT, st);
+    }
     if ((rc = copy_in(ctx, s, e.s, b))) return rc;
   } else {
     e_pivots<T>(st, e, 1, N, pc == kPcSsor, omega);

@@ -88,10 +88,10 @@ __device__ __forceinline__ u16x8 load_t8(const uint16_t* __restrict__ B, int K, 
                                          bool vec_ok) {
   u16x8 v;
   if (row < K && vec_ok && k + 7 < K) {
-    v = *reinterpret_cast<const u16x8*>(B + (size_t)row * K + k);
+    v = *as_global(reinterpret_cast<const u16x8*>(B + (size_t)row * K + k));
   } else {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) v[e] = (row < K && k + e < K) ? B[(size_t)row * K + k + e] : 0;
+    for (int e = 0; e < 8; ++e) v[e] = (row < K && k + e < K) ? as_global(B)[(size_t)row * K + k + e] : 0;
   }
   return v;
 }
@@ -197,7 +197,7 @@ __global__ void __launch_bounds__(256) k_e_dct_mfma(DArgs a) {
           const bool in = c < K && r < R;
           if (a.stage == 1 && in)
             y = (c == 0 && r == 0) ? 0.0f
-                                   : (float)((double)y / (d.tabM->lam[c] + d.tabN->lam[r]));
+                                   : (float)((double)y / (as_global(d.tabM->lam)[c] + as_global(d.tabN->lam)[r]));
           if (a.stage == 3 && in) {
             const size_t o = (size_t)c * R + r;
             if (iso && iso[o]) y = 0.0f;
@@ -318,7 +318,7 @@ __global__ void __launch_bounds__(256, 2) k_e_dct_eo(DArgs a) {
       // (second forward stage and the first inverse stage).
       const MapDesc& dm = a.desc[t.m];
       const float nr = (float)sqrt(st.rr) * 1.0000001f;
-      const float lmin = (float)fmin(dm.tabM->lam[1], dm.tabN->lam[1]);
+      const float lmin = (float)fmin(as_global(dm.tabM->lam)[1], as_global(dm.tabN->lam)[1]);
       const float b01 = 2.0f * nr, b23 = nr / lmin * 1.0000001f;
       xs = fp16_scale(a.stage <= 1 ? b01 : b23);
       inv_xs = 1.0f / xs;
@@ -348,7 +348,7 @@ __global__ void __launch_bounds__(256, 2) k_e_dct_eo(DArgs a) {
         const uint16_t* T = plane ? T1 : T0;
         const uint16_t* src = INV ? T + (size_t)(c0 + row) * n + (half ? h : 0) + k0 + 8 * bq
                                   : T + (size_t)((half ? h : 0) + c0 + row) * h + k0 + 8 * bq;
-        sT[p] = *reinterpret_cast<const u16x8*>(src);
+        sT[p] = *as_global(reinterpret_cast<const u16x8*>(src));
       }
     };
     auto stash = [&]() {
@@ -473,7 +473,7 @@ __global__ void __launch_bounds__(256, 2) k_e_dct_eo(DArgs a) {
         const int r = rb + e;
         if (a.stage == 1)
           yy = (c == 0 && r == 0) ? 0.0f
-                                  : (float)((double)yy / (d.tabM->lam_split[c] + d.tabN->lam_split[r]));
+                                  : (float)((double)yy / (as_global(d.tabM->lam_split)[c] + as_global(d.tabN->lam_split)[r]));
         if (a.stage == 3) {
           const size_t o = (size_t)c * R + r;
           if (iso && iso[o]) yy = 0.0f;
@@ -573,7 +573,7 @@ __global__ void __launch_bounds__(256) k_e_dct_fma(DArgs a) {
       for (int e = 0; e < 4; ++e) {
         const int k = k0 + lk + e, rr = r0 + lrow, cc = c0 + lrow;
         Xs[lk + e][lrow] = (rr < R && k < K) ? X[(size_t)rr * K + k] : T(0);
-        Bs[lk + e][lrow] = (cc < K && k < K) ? B[(size_t)cc * K + k] : T(0);
+        Bs[lk + e][lrow] = (cc < K && k < K) ? as_global(B)[(size_t)cc * K + k] : T(0);
       }
       __syncthreads();
 #pragma unroll
@@ -603,7 +603,7 @@ __global__ void __launch_bounds__(256) k_e_dct_fma(DArgs a) {
         if (r >= R) continue;
         const size_t o = (size_t)c * R + r;
         T v = acc[i][j];
-        if (a.stage == 1) v = (c == 0 && r == 0) ? T(0) : (T)((double)v / (d.tabM->lam[c] + d.tabN->lam[r]));
+        if (a.stage == 1) v = (c == 0 && r == 0) ? T(0) : (T)((double)v / (as_global(d.tabM->lam)[c] + as_global(d.tabN->lam)[r]));
         if (a.stage == 3) {
           if (iso && iso[o]) v = T(0);
           part += (double)rv[o] * (double)v;

@@ -1,4 +1,4 @@
-// Device helpers: deterministic FP64 block reductions.
+// Device helpers: deterministic FP64 block reductions; global-memory views.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -6,6 +6,19 @@
 #include "lpu_internal.h"
 
 namespace lpu {
+
+// Global-memory view of a pointer read from a descriptor in memory (the
+// compiler cannot tell its address space and would emit flat loads, which
+// also count against the LDS wait counter, so every wait for an LDS read in
+// the same wave would wait for them too).
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* as_global(const T* p) {
+  return (const __attribute__((address_space(1))) T*)(p);
+}
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* as_global(T* p) {
+  return (__attribute__((address_space(1))) T*)(p);
+}
 
 // Sum NV values over the block; the result is valid in thread 0.  The shape of
 // the tree is fixed, so the result does not depend on scheduling.
