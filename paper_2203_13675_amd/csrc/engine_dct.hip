@@ -278,7 +278,7 @@ __global__ void __launch_bounds__(256, 2) k_e_dct_eo(DArgs a) {
   constexpr int NC = KS / 8;                       // 16-byte chunks per LDS row
   constexpr int kA = 128 * KS, kB = 64 * KS;       // elements of one A / B half-plane
   constexpr int kStage = NP * 2 * (kA + kB) * 2;   // bytes of staged operands
-  constexpr int kXchg = 2 * 16 * 64 * 16;          // bytes of the inverse's v exchange
+  constexpr int kXchg = 2 * 2 * 16 * 64 * 16;      // bytes of the inverse's u/v exchange
   constexpr int kSmem = kStage > kXchg ? kStage : kXchg;
   constexpr int VPT = IN16 ? 8 : 4;                // X staging: values per thread and load
   constexpr int TPR = KS / VPT;                    // X staging: threads per row
@@ -460,26 +460,37 @@ __global__ void __launch_bounds__(256, 2) k_e_dct_eo(DArgs a) {
       }
       }  // ks
     }
-    // epilogue: lane holds D[row 4*(lane/16) + e][col lane mod 16] of each 16x16 tile
+    // epilogue: lane holds D[row 4*(lane/16) + e][col lane mod 16] of each 16x16 tile,
+    // i.e. outputs (c, rb .. rb+3) with rb a multiple of 4
     const MapDesc& d = a.desc[t.m];
     const float* rv = reinterpret_cast<const float*>(a.rvec) + t.off;
     const unsigned char* iso = (a.iso && d.use_iso) ? a.iso + t.off : nullptr;
+    const auto* lamMs = as_global(d.tabM->lam_split);
+    const auto* lamNs = as_global(d.tabN->lam_split);
     double part = 0.0;
     auto emit = [&](int c, int rb, const float (&y)[4]) {
-      float v[4];
+      float v[4] = {y[0], y[1], y[2], y[3]};
+      if (a.stage == 1) {
+        // spectrum ./ Lambda with the zero mode dropped; an FP32 reciprocal
+        // (the preconditioner stays one fixed linear map)
+        const float lc = (float)lamMs[c];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        float yy = y[e];
-        const int r = rb + e;
-        if (a.stage == 1)
-          yy = (c == 0 && r == 0) ? 0.0f
-                                  : (float)((double)yy / (as_global(d.tabM->lam_split)[c] + as_global(d.tabN->lam_split)[r]));
-        if (a.stage == 3) {
-          const size_t o = (size_t)c * R + r;
-          if (iso && iso[o]) yy = 0.0f;
-          part += (double)rv[o] * (double)yy;
+        for (int e = 0; e < 4; ++e) {
+          const float l = lc + (float)lamNs[rb + e];
+          v[e] = (c == 0 && rb + e == 0) ? 0.0f : v[e] * __builtin_amdgcn_rcpf(l);
         }
-        v[e] = yy;
+      }
+      if (a.stage == 3) {
+        // zero on isolated pixels; FP64 partial of r^T s (four outputs at once)
+        const size_t o = (size_t)c * R + rb;
+        const f32x4 r4 = *as_global(reinterpret_cast<const f32x4*>(rv + o));
+        const unsigned int z = iso ? *as_global(reinterpret_cast<const unsigned int*>(iso + o)) : 0u;
+        const float rr4[4] = {r4[0], r4[1], r4[2], r4[3]};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          if ((z >> (8 * e)) & 0xffu) v[e] = 0.0f;
+          part += (double)rr4[e] * (double)v[e];
+        }
       }
       if (OUT16) {
         u16x4 hv;
@@ -502,31 +513,28 @@ __global__ void __launch_bounds__(256, 2) k_e_dct_eo(DArgs a) {
         }
       }
     } else {
-      // v (half 1) goes through LDS to the waves holding u for the same rows
-      f32x4* xv = reinterpret_cast<f32x4*>(smem) + (size_t)(w & 1) * 16 * 64;
+      // u (half 0) and v (half 1) of the same rows meet through LDS: the
+      // waves of half 0 write u + v to output c, those of half 1 write
+      // u - v to output n-1-c
+      f32x4* xg = reinterpret_cast<f32x4*>(smem);  // [half][row group][16 tiles][64 lanes]
       __syncthreads();  // every wave is done reading the staged operands
-      if (hf == 1) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < 4; ++i)
 #pragma unroll
-          for (int j = 0; j < 4; ++j) xv[(i * 4 + j) * 64 + lane] = acc[i][j];
-      }
+        for (int j = 0; j < 4; ++j) xg[((hf * 2 + (w & 1)) * 16 + i * 4 + j) * 64 + lane] = acc[i][j];
       __syncthreads();
-      if (hf == 0) {
+      const int oh = hf ^ 1;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int c = c0 + 16 * j + lr;
+      for (int j = 0; j < 4; ++j) {
+        const int c = c0 + 16 * j + lr;
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const f32x4 v = xv[(i * 4 + j) * 64 + lane];
-            const float yp[4] = {(acc[i][j][0] + v[0]) * inv_xs, (acc[i][j][1] + v[1]) * inv_xs,
-                                 (acc[i][j][2] + v[2]) * inv_xs, (acc[i][j][3] + v[3]) * inv_xs};
-            const float ym[4] = {(acc[i][j][0] - v[0]) * inv_xs, (acc[i][j][1] - v[1]) * inv_xs,
-                                 (acc[i][j][2] - v[2]) * inv_xs, (acc[i][j][3] - v[3]) * inv_xs};
-            const int rb = t.r0 + wr + 16 * i + 4 * kq;
-            emit(c, rb, yp);
-            emit(n - 1 - c, rb, ym);
-          }
+        for (int i = 0; i < 4; ++i) {
+          const f32x4 o = xg[((oh * 2 + (w & 1)) * 16 + i * 4 + j) * 64 + lane];  // the other half
+          const float y[4] = {(hf ? o[0] - acc[i][j][0] : acc[i][j][0] + o[0]) * inv_xs,
+                              (hf ? o[1] - acc[i][j][1] : acc[i][j][1] + o[1]) * inv_xs,
+                              (hf ? o[2] - acc[i][j][2] : acc[i][j][2] + o[2]) * inv_xs,
+                              (hf ? o[3] - acc[i][j][3] : acc[i][j][3] + o[3]) * inv_xs};
+          emit(hf ? n - 1 - c : c, t.r0 + wr + 16 * i + 4 * kq, y);
         }
       }
     }
