@@ -131,6 +131,17 @@ def main():
     ktimes = ctx.kernel_timing_report()
     ctx.kernel_timing("off")
     warm_split = {k: v["ms"] for k, v in ktimes.items()}
+    # every class's algorithmic rate over its launches in the timing pass
+    classes = {}
+    for k, v in ktimes.items():
+        if v["ms"] <= 0 or v["bytes"] <= 0:
+            continue
+        gbs = v["bytes"] / (v["ms"] * 1e-3) / 1e9
+        c = {"launches": v["launches"], "avg_launch_us": v["ms"] * 1e3 / max(v["launches"], 1),
+             "alg_GBps": gbs, "hbm_frac": gbs / PEAK_HBM_GBS}
+        if v["flops"] > 0:
+            c["TFLOPps"] = v["flops"] / (v["ms"] * 1e-3) / 1e12
+        classes[k] = c
 
     value = total_px / dt / 1e6
     inner = sum(s["inner_iters_total"] for s in stats)
@@ -148,7 +159,18 @@ def main():
                   "alg_bytes_per_launch": kt["bytes"] / launches,
                   "alg_flops_per_launch": kt["flops"] / launches,
                   "avg_launch_us": per_launch_s * 1e6, "launches": kt["launches"]}
-        if kt["flops"] > 0 and name.startswith("dct"):
+        # the binding roof is the one whose time at peak is longer: MFMA when
+        # the launch's flops per algorithmic byte exceed the ridge point
+        # (peak flops / peak bandwidth), HBM otherwise
+        ridge = PEAK_FP16_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9)
+        intensity = kt["flops"] / kt["bytes"] if kt["bytes"] > 0 else float("inf")
+        common["flops_per_byte"] = intensity
+        common["ridge_flops_per_byte"] = ridge
+        if kt["flops"] > 0:
+            tf = kt["flops"] / launches / per_launch_s / 1e12
+            common["mfma_achieved_tflops"] = tf
+            common["mfma_frac"] = tf / PEAK_FP16_TFLOPS
+        if kt["flops"] > 0 and intensity >= ridge:
             ach = kt["flops"] / launches / per_launch_s / 1e12
             roofline = {"bound": "mfma", "achieved": ach, "peak": PEAK_FP16_TFLOPS,
                         "unit": "TFLOP/s", "frac": ach / PEAK_FP16_TFLOPS, **common}
@@ -171,6 +193,7 @@ def main():
         "pcg_iters_per_step": inner, "cg_iters_per_s": inner / dt,
         "worst_final_relres": worst_relres,
         "kernel_ms_per_step": warm_split,
+        "kernel_classes": classes,
         "ms_per_step_timing_pass": t_eager * 1e3,
         "issue": "graph" if a.graph else "eager",
         "roofline": roofline,

@@ -27,13 +27,13 @@ template <typename T> void e_diag(hipStream_t, const Engine&, int, bool);
 template <typename T> void e_rhs(hipStream_t, const Engine&, int, int);
 template <typename T> void e_pass(hipStream_t, const Engine&, int, int);
 template <typename T> void e_resid(hipStream_t, const Engine&, int, int, bool);
-template <typename T> void e_spmv(hipStream_t, const Engine&, int, int);
-template <typename T> void e_update(hipStream_t, const Engine&, int, int);
+template <typename T> void e_spmv(hipStream_t, const Engine&, int, int, bool);
+template <typename T> void e_update(hipStream_t, const Engine&, int, int, bool);
 template <typename T> void e_apply(hipStream_t, const Engine&, int);
 void e_finish(hipStream_t st, const Engine& e, int op, int expect, int mode, bool pointwise,
               bool tail_single);
 void e_dct_stage(hipStream_t st, const Engine& e, int ndtiles, int stage, int expect, int kind,
-                 const void* X, void* Out, const void* rvec);
+                 const void* X, void* Out, const void* rvec, int fin_mode);
 int egrid(const Engine& e, int ntiles);
 int dct_grid_for(const Engine& e, int ndtiles);
 template <typename T> void e_pivots(hipStream_t, const Engine&, int, int, bool, double);
@@ -67,7 +67,7 @@ static double now_ms() {
 // engine set-up
 // ---------------------------------------------------------------------------
 static void engine_free(Engine& e) {
-  void* ptrs[] = {e.desc, e.ms, e.tile_map, e.dtile_map, e.act, e.dact, e.mact, e.counts,
+  void* ptrs[] = {e.desc, e.ms, e.tile_map, e.dtile_map, e.act, e.dact, e.mact, e.fcnt, e.gcnt, e.counts,
                   e.dx, e.dy, e.phi_prev, e.r64, e.U, e.V, e.aux, e.x[0], e.x[1], e.d[0],
                   e.d[1], e.r, e.s, e.q, e.b, e.t1, e.t2, e.iso, e.P};
   for (void* p : ptrs)
@@ -143,7 +143,7 @@ static int engine_setup(lp_unwrap_ctx* ctx, int n, const lpu_map* maps, int elem
   release_graphs(ctx);  // captured graphs hold the previous layout's launch shapes
   std::vector<MapDesc> hd(n);
   long long px = 0;
-  int tiles = 0, dtiles = 0, maxN = 1;
+  int tiles = 0, dtiles = 0, maxN = 1, groups = 0;
   for (int m = 0; m < n; ++m) {
     MapDesc& d = hd[m];
     std::memset(&d, 0, sizeof(d));
@@ -159,6 +159,10 @@ static int engine_setup(lp_unwrap_ctx* ctx, int n, const lpu_map* maps, int elem
     d.ndt = ((d.M + dct_trows - 1) / dct_trows) * ((d.N + ccols - 1) / ccols);
     d.dtile0 = dtiles;
     dtiles += d.ndt;
+    d.gb = groups;
+    groups += (d.ntiles + kArriveGroup - 1) / kArriveGroup;
+    d.gbd = groups;
+    groups += (d.ndt + kArriveGroup - 1) / kArriveGroup;
     d.off = px;
     px += ((long long)d.M * d.N + 63) / 64 * 64;
     d.psi = maps[m].psi;
@@ -192,6 +196,9 @@ static int engine_setup(lp_unwrap_ctx* ctx, int n, const lpu_map* maps, int elem
     const long long dcap = (long long)dtiles + 8LL * (n + 1) * 256 + 64;
     A((void**)&e.dact, 4 * (size_t)(2 * dcap));
     A((void**)&e.mact, 4 * (size_t)n);
+    A((void**)&e.fcnt, 4 * (size_t)n);
+    // groups <= tiles / G + dtiles / G + 2 n for any layout within these capacities
+    A((void**)&e.gcnt, 4 * ((size_t)(tiles + dtiles) / kArriveGroup + 2 * (size_t)n + 8));
     A((void**)&e.counts, 64);
     A((void**)&e.dx, 8 * (size_t)cpx);
     A((void**)&e.dy, 8 * (size_t)cpx);
@@ -220,6 +227,11 @@ static int engine_setup(lp_unwrap_ctx* ctx, int n, const lpu_map* maps, int elem
     if (hipMemset(e.iso, 0, (size_t)cpx) != hipSuccess)
       return set_error(ctx, LPU_ERR_HIP, "hipMemset");
   }
+  // arrival counters start at zero (every launch leaves them so; cleared
+  // here as well, outside any graph capture)
+  if (hipMemsetAsync(e.fcnt, 0, 4 * (size_t)n, ctx->stream) != hipSuccess ||
+      hipMemsetAsync(e.gcnt, 0, 4 * (size_t)std::max(groups, 1), ctx->stream) != hipSuccess)
+    return set_error(ctx, LPU_ERR_HIP, "hipMemsetAsync");
   e.n_maps = n;
   e.total_px = px;
   e.total_tiles = tiles;
@@ -349,15 +361,20 @@ struct Pcg {
 
   bool pointwise() const { return pc == kPcNone || pc == kPcJacobi; }
 
-  void tail(hipStream_t st, int ndt, int nmaps, int expect) {
+  // Preconditioner apply s = M^-1 r for the maps in state `expect`, then the
+  // per-map finisher of r^T s with FinishMode `mode` (inside the last DCT
+  // stage for the even/odd kernels, as a launch of its own otherwise).
+  void tail(hipStream_t st, int ndt, int nmaps, int expect, int mode) {
     Engine& e = ctx->eng;
     KTimer& kt = ctx->kt;
+    bool fused = false;
     if (pc == kPcDct) {
       const void* in[4] = {e.r, e.t1, e.t2, e.t1};
       void* out[4] = {e.t1, e.t2, e.t1, e.s};
+      fused = dct_kind >= 4;
       for (int s = 0; s < 4; ++s) {
         const int ev = kt.begin(LPU_KC_DCT, st);
-        e_dct_stage(st, e, ndt, s, expect, dct_kind, in[s], out[s], e.r);
+        e_dct_stage(st, e, ndt, s, expect, dct_kind, in[s], out[s], e.r, mode);
         kt.end(ev, LPU_KC_DCT, st);
       }
     } else {
@@ -365,6 +382,7 @@ struct Pcg {
       e_sweep<T>(st, e, nmaps, e.max_n, expect, pc == kPcSsor, omega, e.r, e.s, e.t1);
       kt.end(ev, LPU_KC_SWEEP, st);
     }
+    if (!fused) fin(st, kFinTailH, expect, mode);
   }
 
   void fin(hipStream_t st, int op, int expect, int mode = kFinishNone) {
@@ -378,18 +396,14 @@ struct Pcg {
   void body(hipStream_t st, int nt, int nd, int nm) {
     Engine& e = ctx->eng;
     KTimer& kt = ctx->kt;
+    // the finishers of alpha and of the update run inside the two launches
     int ev = kt.begin(LPU_KC_SPMV, st);
-    e_spmv<T>(st, e, nt, pc);
+    e_spmv<T>(st, e, nt, pc, true);
     kt.end(ev, LPU_KC_SPMV, st);
-    fin(st, kFinAlphaH, kRun);
     ev = kt.begin(LPU_KC_UPDATE, st);
-    e_update<T>(st, e, nt, pc);
+    e_update<T>(st, e, nt, pc, true);
     kt.end(ev, LPU_KC_UPDATE, st);
-    fin(st, kFinUpdateH, kRun);
-    if (!pointwise()) {
-      tail(st, nd, nm, kRun);
-      fin(st, kFinTailH, kRun, kFinishIter);
-    }
+    if (!pointwise()) tail(st, nd, nm, kRun, kFinishIter);
   }
 
   // Issue K iterations: as K launches of a captured graph of the body (one
@@ -461,8 +475,7 @@ struct Pcg {
     kt.end(ev, LPU_KC_INIT, st);
     fin(st, kFinInitH, kRun);
     if (!pw) {
-      tail(st, nd, (int)set.size(), kInitPc);
-      fin(st, kFinTailH, kInitPc, kFinishInit);
+      tail(st, nd, (int)set.size(), kInitPc, kFinishInit);
     }
     long long K = 4;
     const long long Kcap = std::max(2, ctx->tune.max_batch_iters);
@@ -475,8 +488,7 @@ struct Pcg {
       kt.end(ev, LPU_KC_CONFIRM, st);
       fin(st, kFinConfirmH, kConfirm);
       if (!pw) {
-        tail(st, nd, (int)set.size(), kConfirmPc);
-        fin(st, kFinTailH, kConfirmPc, kFinishConfirm);
+        tail(st, nd, (int)set.size(), kConfirmPc, kFinishConfirm);
       }
       if ((rc = read_states(ctx))) return rc;
       std::vector<int> still;
@@ -864,7 +876,7 @@ int step_precond(lp_unwrap_ctx* ctx, int M, int N, int pc, int dct_mode, double 
     void* out[4] = {e.t1, e.t2, e.t1, e.s};
     for (int k = 0; k < 4; ++k) {
       const int ev = ctx->kt.begin(LPU_KC_DCT, st);
-      e_dct_stage(st, e, e.total_dtiles, k, kRun, kind, in[k], out[k], e.r);
+      e_dct_stage(st, e, e.total_dtiles, k, kRun, kind, in[k], out[k], e.r, 0);
       ctx->kt.end(ev, LPU_KC_DCT, st);
     }
     if ((rc = copy_in(ctx, s, e.s, b))) return rc;

@@ -24,6 +24,7 @@ constexpr int kTH = 16;   // default stencil tile height (rows), marched by the 
 constexpr int kDT = 64;   // DCT output tile (64 x 64)
 constexpr int kEngineGrid = 4096;  // default cap on the blocks of the grid-stride tile kernels
 constexpr int kDctGrid = 2048;     // default cap on the blocks of a DCT stage
+constexpr int kArriveGroup = 32;   // tiles per first-level arrival counter of the fused finishers
 constexpr int kNumSlots = 4;       // partial-sum slots
 
 // DCT tables of one size n as seen by the kernels.
@@ -55,6 +56,7 @@ struct MapDesc {
   int th;                     // stencil tile height (rows)
   int tiles_x, ntiles, tile0;  // stencil tiles
   int ndt, dtile0;             // DCT tiles (same count in every stage)
+  int gb, gbd;                 // first arrival-group counter of the stencil / DCT tiles
   int use_iso;                 // zero the preconditioner output on isolated pixels
   long long off;               // element offset of this map in the work vectors
   const double* psi;           // caller's wrapped phase
@@ -97,6 +99,8 @@ struct Engine {
   long long dlist_cap = 0;   // capacity of each of the two DCT lists
   int dct_trows = kDT;       // DCT output tile rows (64 dense, 128 even/odd)
   int* mact = nullptr;       // active maps (sweep kernels)
+  int* fcnt = nullptr;       // per-map arrival counters of the fused finishers (zero between launches)
+  int* gcnt = nullptr;       // per-group arrival counters (groups of kArriveGroup tiles of one map)
   int* counts = nullptr;     // [0] active tiles, [1] DCT list (even stages), [2] active
                              // maps, [3] DCT list (odd stages)
   int* hcounts = nullptr;    // pinned

@@ -15,6 +15,7 @@
 
 #include "lpu_internal.h"
 #include "lpu_device.h"
+#include "lpu_finish.h"
 
 namespace lpu {
 
@@ -39,6 +40,9 @@ struct DArgs {
   int stage, expect;
   int trows;  // output tile rows: 64 (dense kernels) or 128 (even/odd kernels)
   int cidx;   // counts[] slot holding the length of `dact`
+  int *fcnt, *gcnt;  // arrival counters of the fused finisher
+  int fin_mode;  // last stage of the even/odd kernels: 0, or the FinishMode of
+                 // the fused finisher (the map's r^T s, beta and stop tests)
 };
 
 struct DTile {
@@ -287,6 +291,8 @@ __global__ void __launch_bounds__(256, 2) k_e_dct_eo(DArgs a) {
   constexpr int TP = NP * 2 * 64 / SEGS;           // table staging passes
   __shared__ __attribute__((aligned(16))) unsigned char smem[kSmem];
   __shared__ double red[4];
+  __shared__ double fred[3 * 4];
+  __shared__ int fflag;
   uint16_t* As = reinterpret_cast<uint16_t*>(smem);  // [plane][half][128 x KS]
   uint16_t* Bs = As + NP * 2 * kA;                   // [plane][half][64 x KS]
   const int nact = a.counts[a.cidx];
@@ -541,7 +547,12 @@ __global__ void __launch_bounds__(256, 2) k_e_dct_eo(DArgs a) {
     if (a.stage == 3) {
       double vv[1] = {part};
       block_sum<1>(vv, red);
-      if (tid == 0) a.P[1 * a.pstride + g] = vv[0];
+      if (tid == 0) store_partial(a.P + 1 * a.pstride + g, vv[0]);
+      if (a.fin_mode && last_arrival(a.fcnt, a.gcnt, t.m, g - a.desc[t.m].dtile0,
+                                       a.desc[t.m].ndt, a.desc[t.m].gbd, &fflag)) {
+        finish_map(a.desc, a.ms, a.P, a.pstride, t.m, kFinTail, a.fin_mode, 0, 0, fred);
+        rearm(a.fcnt, t.m);
+      }
     }
   }
 }
@@ -638,8 +649,12 @@ int dct_grid_for(const Engine& e, int ndtiles) {
 }
 
 void e_dct_stage(hipStream_t st, const Engine& e, int ndtiles, int stage, int expect, int kind,
-                 const void* X, void* Out, const void* rvec) {
+                 const void* X, void* Out, const void* rvec, int fin_mode) {
   DArgs a;
+  a.fcnt = e.fcnt;
+  a.gcnt = e.gcnt;
+  // the finisher rides on the last stage of the even/odd kernels only
+  a.fin_mode = (stage == 3 && kind >= 4) ? fin_mode : 0;
   a.desc = e.desc;
   a.ms = e.ms;
   a.dtile_map = e.dtile_map;

@@ -17,6 +17,7 @@
 
 #include "lpu_internal.h"
 #include "lpu_device.h"
+#include "lpu_finish.h"
 
 namespace lpu {
 
@@ -271,6 +272,8 @@ struct EArgs {
   void *U, *V, *aux, *x0, *x1, *d0, *d1, *r, *s, *q, *b;
   double *dx, *dy, *phi_prev, *r64;
   const unsigned char* iso;
+  int *fcnt, *gcnt;  // arrival counters of the finisher fused into the tile kernel
+  int fuse_pw;  // -1: no fused finisher; else its pointwise-preconditioner flag
 };
 
 #define TILE_LOOP(A)                                                  \
@@ -517,6 +520,8 @@ __global__ void __launch_bounds__(64) k_e_resid(EArgs A) {
 // spmv: d_new = s + beta d_old; q = A d_new; partial d^T q
 template <typename T, int PC, int TH>
 __global__ void __launch_bounds__(64) k_e_spmv(EArgs A) {
+  __shared__ double fred[3];
+  __shared__ int fflag;
   TILE_LOOP(A) {
     const int g = A.act[t_];
     const TilePos tp = tile_pos(A.desc, A.tile_map, g);
@@ -554,7 +559,13 @@ __global__ void __launch_bounds__(64) k_e_spmv(EArgs A) {
           sdq += (double)dv * (double)qv;
         });
     sdq = wave_sum(sdq);
-    if (lane_id() == 0) A.P[0 * A.pstride + g] = sdq;
+    if (lane_id() == 0) store_partial(A.P + 0 * A.pstride + g, sdq);
+    const MapDesc& dm = A.desc[tp.m];
+    if (A.fuse_pw >= 0 &&
+        last_arrival(A.fcnt, A.gcnt, tp.m, g - dm.tile0, dm.ntiles, dm.gb, &fflag)) {
+      finish_map(A.desc, A.ms, A.P, A.pstride, tp.m, kFinAlpha, kFinishNone, A.fuse_pw, 1, fred);
+      rearm(A.fcnt, tp.m);
+    }
   }
 }
 
@@ -562,6 +573,8 @@ __global__ void __launch_bounds__(64) k_e_spmv(EArgs A) {
 // l is a multiple of the replacement period; pointwise s; partials r.r, r.s
 template <typename T, int PC, int TH>
 __global__ void __launch_bounds__(64) k_e_update(EArgs A) {
+  __shared__ double fred[3];
+  __shared__ int fflag;
   TILE_LOOP(A) {
     const int g = A.act[t_];
     const TilePos tp = tile_pos(A.desc, A.tile_map, g);
@@ -653,8 +666,14 @@ __global__ void __launch_bounds__(64) k_e_update(EArgs A) {
     srr = wave_sum(srr);
     srs = wave_sum(srs);
     if (lane_id() == 0) {
-      A.P[0 * A.pstride + g] = srr;
-      A.P[1 * A.pstride + g] = srs;
+      store_partial(A.P + 0 * A.pstride + g, srr);
+      store_partial(A.P + 1 * A.pstride + g, srs);
+    }
+    const MapDesc& dm = A.desc[tp.m];
+    if (A.fuse_pw >= 0 &&
+        last_arrival(A.fcnt, A.gcnt, tp.m, g - dm.tile0, dm.ntiles, dm.gb, &fflag)) {
+      finish_map(A.desc, A.ms, A.P, A.pstride, tp.m, kFinUpdate, kFinishNone, A.fuse_pw, 1, fred);
+      rearm(A.fcnt, tp.m);
     }
   }
 }
@@ -680,161 +699,14 @@ __global__ void __launch_bounds__(64) k_e_apply(EArgs A) {
 // Finisher: one block per map, fixed-order sums of the map's partials, then
 // the map's PCG state advances.
 // ---------------------------------------------------------------------------
-enum FinOp : int {
-  kFinInit = 0,     // slots 0,1,2 over stencil tiles: r.r, r.s, b.b
-  kFinAlpha = 1,    // slot 0: d^T q
-  kFinUpdate = 2,   // slots 0,1: r.r, r.s
-  kFinConfirm = 3,  // slots 0,1: r.r, r.s
-  kFinTail = 4,     // slot 1 over DCT tiles (or one sweep partial): r.s
-  kFinSum2 = 5      // slots 0,1 over stencil tiles -> rr, bb (no state change)
-};
-
-__device__ inline void map_finish(MapState& s, int mode, double rs) {
-  if (mode == kFinishIter) {
-    s.delta_old = s.delta_new;
-    s.delta_new = rs;
-    s.beta = rs / s.delta_old;
-    s.l += 1;
-  } else if (mode == kFinishConfirm) {
-    s.delta_new = rs;
-    s.beta = rs / s.delta_old;
-  } else {
-    s.delta_new = rs;
-    s.delta0 = rs;
-    s.beta = 0.0;
-    s.thr_delta = s.eps2 * rs;
-  }
-  s.nfinish += 1;
-  int st = kRun;
-  if (s.rule == LPU_STOP_PAPER) {
-    if (!(s.delta_new > s.thr_delta)) st = kDone;
-  } else if (s.rr <= s.thr_rr && (s.replaced || mode != kFinishIter)) {
-    st = kDone;
-  }
-  if (st == kRun) {
-    if (!isfinite(s.delta_new) || s.delta_new < 0.0 || !isfinite(s.beta)) st = kBreakdown;
-    else if (s.l >= s.l_max) st = kCap;
-  }
-  s.state = st;
-}
-
-// Stagnation of a mixed-precision inner solve.  Checkpoints are the true
-// residuals the iteration forms anyway (periodic replacements and failed
-// confirmations).  Two checkpoints at least chk_gap iterations apart are
-// compared (chk_gap = min(MN, max(period, 256)): in exact arithmetic CG ends
-// within MN iterations, and over shorter spans the residual norm of CG need
-// not decrease); if the later one is still above the bound and not at least
-// 10 % (in norm) below the earlier one, the FP32 iterate has reached what its
-// precision can resolve and the solve stops; the FP64 refinement around it
-// continues from its iterate.
-__device__ inline bool stagnated(MapState& s, double rr_true) {
-  if (!s.stall || s.rule != LPU_STOP_RELRES || rr_true <= s.thr_rr) return false;
-  if (s.rr_chk <= 0.0) {
-    s.rr_chk = rr_true;
-    s.l_chk = s.l;
-    return false;
-  }
-  if (s.l - s.l_chk < s.chk_gap) return false;
-  const bool stuck = rr_true >= 0.81 * s.rr_chk;
-  s.rr_chk = rr_true;
-  s.l_chk = s.l;
-  return stuck;
-}
-
-template <int NS>
-__device__ __forceinline__ void fin_sums(const double* __restrict__ P, long long pstride, int first,
-                                         int count, const int* slots, double (&out)[NS],
-                                         double* smem) {
-#pragma unroll
-  for (int k = 0; k < NS; ++k) {
-    double v = 0.0;
-    for (int t = threadIdx.x; t < count; t += blockDim.x) v += P[slots[k] * pstride + first + t];
-    out[k] = v;
-  }
-  block_sum<NS>(out, smem);
-}
-
 __global__ void __launch_bounds__(256) k_e_finish(const MapDesc* __restrict__ desc, MapState* ms,
                                                   const double* __restrict__ P, long long pstride,
                                                   int op, int expect, int mode, int pointwise,
                                                   int tail_single) {
   __shared__ double red[3 * 4];
   const int m = blockIdx.x;
-  MapState& s = ms[m];
-  if (expect >= 0 && s.state != expect) return;
-  const MapDesc& d = desc[m];
-  double v[3] = {0.0, 0.0, 0.0};
-  if (op == kFinInit) {
-    const int sl[3] = {0, 1, 2};
-    fin_sums<3>(P, pstride, d.tile0, d.ntiles, sl, v, red);
-  } else if (op == kFinAlpha) {
-    const int sl[1] = {0};
-    double w[1];
-    fin_sums<1>(P, pstride, d.tile0, d.ntiles, sl, w, red);
-    v[0] = w[0];
-  } else if (op == kFinTail) {
-    const int sl[1] = {1};
-    double w[1];
-    fin_sums<1>(P, pstride, d.dtile0, tail_single ? 1 : d.ndt, sl, w, red);
-    v[0] = w[0];
-  } else {
-    const int sl[2] = {0, 1};
-    double w[2];
-    fin_sums<2>(P, pstride, d.tile0, d.ntiles, sl, w, red);
-    v[0] = w[0];
-    v[1] = w[1];
-  }
-  if (threadIdx.x != 0) return;
-  switch (op) {
-    case kFinInit:
-      s.rr = v[0];
-      s.bb = v[2];
-      s.thr_rr = s.tol2 * v[2];
-      s.l = 0;
-      s.replaced = 1;
-      if (v[2] == 0.0) s.state = kDone;
-      else if (pointwise) map_finish(s, kFinishInit, v[1]);
-      else s.state = kInitPc;
-      break;
-    case kFinAlpha:
-      s.dq = v[0];
-      if (!(v[0] > 0.0) || !isfinite(v[0])) s.state = kBreakdown;
-      else s.alpha = s.delta_new / v[0];
-      break;
-    case kFinUpdate: {
-      const bool replace = (s.l % s.period) == 0;
-      s.rr = v[0];
-      s.replaced = replace ? 1 : 0;
-      if (replace && stagnated(s, v[0])) {
-        s.delta_old = s.delta_new;
-        s.l += 1;  // the iterate of this update is the one returned
-        s.state = kStall;
-      } else if (s.rule == LPU_STOP_RELRES && !replace && v[0] <= s.thr_rr) {
-        s.delta_old = s.delta_new;
-        s.l += 1;
-        s.state = kConfirm;
-      } else if (pointwise) {
-        map_finish(s, kFinishIter, v[1]);
-      }
-    } break;
-    case kFinConfirm:
-      s.rr = v[0];
-      s.replaced = 1;
-      if (v[0] <= s.thr_rr) s.state = kDone;
-      else if (stagnated(s, v[0])) s.state = kStall;
-      else if (pointwise) map_finish(s, kFinishConfirm, v[1]);
-      else s.state = kConfirmPc;
-      break;
-    case kFinTail:
-      s.rs = v[0];
-      s.amax[1] = s.amax[2] = s.amax[3] = 0.0f;  // scaled-fp16 maxima of this application
-      map_finish(s, mode, v[0]);
-      break;
-    case kFinSum2:
-      s.rr = v[0];
-      s.bb = v[1];
-      break;
-  }
+  if (expect >= 0 && ms[m].state != expect) return;
+  finish_map(desc, ms, P, pstride, m, op, mode, pointwise, tail_single, red);
 }
 
 // ---------------------------------------------------------------------------
@@ -874,6 +746,9 @@ EArgs make_args(const Engine& e) {
   a.phi_prev = e.phi_prev;
   a.r64 = e.r64;
   a.iso = e.iso;
+  a.fcnt = e.fcnt;
+  a.gcnt = e.gcnt;
+  a.fuse_pw = -1;
   return a;
 }
 
@@ -920,40 +795,50 @@ void e_resid(hipStream_t st, const Engine& e, int ntiles, int pc, bool confirm) 
 }
 
 template <typename T, int PC>
-static void e_spmv_pc(hipStream_t st, const Engine& e, int gr) {
+static void e_spmv_pc(hipStream_t st, const Engine& e, int gr, int fuse_pw) {
+  EArgs a = make_args(e);
+  a.fuse_pw = fuse_pw;
   switch (e.th) {
-    case 4: hipLaunchKernelGGL((k_e_spmv<T, PC, 4>), dim3(gr), dim3(64), 0, st, make_args(e)); break;
-    case 8: hipLaunchKernelGGL((k_e_spmv<T, PC, 8>), dim3(gr), dim3(64), 0, st, make_args(e)); break;
-    case 16: hipLaunchKernelGGL((k_e_spmv<T, PC, 16>), dim3(gr), dim3(64), 0, st, make_args(e)); break;
-    case 32: hipLaunchKernelGGL((k_e_spmv<T, PC, 32>), dim3(gr), dim3(64), 0, st, make_args(e)); break;
-    default: hipLaunchKernelGGL((k_e_spmv<T, PC, 0>), dim3(gr), dim3(64), 0, st, make_args(e)); break;
+    case 4: hipLaunchKernelGGL((k_e_spmv<T, PC, 4>), dim3(gr), dim3(64), 0, st, a); break;
+    case 8: hipLaunchKernelGGL((k_e_spmv<T, PC, 8>), dim3(gr), dim3(64), 0, st, a); break;
+    case 16: hipLaunchKernelGGL((k_e_spmv<T, PC, 16>), dim3(gr), dim3(64), 0, st, a); break;
+    case 32: hipLaunchKernelGGL((k_e_spmv<T, PC, 32>), dim3(gr), dim3(64), 0, st, a); break;
+    default: hipLaunchKernelGGL((k_e_spmv<T, PC, 0>), dim3(gr), dim3(64), 0, st, a); break;
   }
 }
 
+// fused: the launch also runs the per-map finisher of its partials (alpha
+// after the SpMV, the update's stop tests and pointwise beta after the update)
 template <typename T>
-void e_spmv(hipStream_t st, const Engine& e, int ntiles, int pc) {
+void e_spmv(hipStream_t st, const Engine& e, int ntiles, int pc, bool fused) {
   const int gr = egrid(e, ntiles);
-  if (pc == kPcNone) e_spmv_pc<T, kPcNone>(st, e, gr);
-  else if (pc == kPcJacobi) e_spmv_pc<T, kPcJacobi>(st, e, gr);
-  else e_spmv_pc<T, kPcDct>(st, e, gr);
+  const int pw = pc == kPcNone || pc == kPcJacobi ? 1 : 0;
+  const int f = fused ? pw : -1;
+  if (pc == kPcNone) e_spmv_pc<T, kPcNone>(st, e, gr, f);
+  else if (pc == kPcJacobi) e_spmv_pc<T, kPcJacobi>(st, e, gr, f);
+  else e_spmv_pc<T, kPcDct>(st, e, gr, f);
 }
 
 template <typename T, int PC>
-static void e_update_pc(hipStream_t st, const Engine& e, int gr) {
+static void e_update_pc(hipStream_t st, const Engine& e, int gr, int fuse_pw) {
+  EArgs a = make_args(e);
+  a.fuse_pw = fuse_pw;
   switch (e.th) {
-    case 4: hipLaunchKernelGGL((k_e_update<T, PC, 4>), dim3(gr), dim3(64), 0, st, make_args(e)); break;
-    case 8: hipLaunchKernelGGL((k_e_update<T, PC, 8>), dim3(gr), dim3(64), 0, st, make_args(e)); break;
-    case 16: hipLaunchKernelGGL((k_e_update<T, PC, 16>), dim3(gr), dim3(64), 0, st, make_args(e)); break;
-    case 32: hipLaunchKernelGGL((k_e_update<T, PC, 32>), dim3(gr), dim3(64), 0, st, make_args(e)); break;
-    default: hipLaunchKernelGGL((k_e_update<T, PC, 0>), dim3(gr), dim3(64), 0, st, make_args(e)); break;
+    case 4: hipLaunchKernelGGL((k_e_update<T, PC, 4>), dim3(gr), dim3(64), 0, st, a); break;
+    case 8: hipLaunchKernelGGL((k_e_update<T, PC, 8>), dim3(gr), dim3(64), 0, st, a); break;
+    case 16: hipLaunchKernelGGL((k_e_update<T, PC, 16>), dim3(gr), dim3(64), 0, st, a); break;
+    case 32: hipLaunchKernelGGL((k_e_update<T, PC, 32>), dim3(gr), dim3(64), 0, st, a); break;
+    default: hipLaunchKernelGGL((k_e_update<T, PC, 0>), dim3(gr), dim3(64), 0, st, a); break;
   }
 }
 
 template <typename T>
-void e_update(hipStream_t st, const Engine& e, int ntiles, int pc) {
+void e_update(hipStream_t st, const Engine& e, int ntiles, int pc, bool fused) {
   const int gr = egrid(e, ntiles);
-  if (pc == kPcJacobi) e_update_pc<T, kPcJacobi>(st, e, gr);
-  else e_update_pc<T, kPcNone>(st, e, gr);
+  const int pw = pc == kPcNone || pc == kPcJacobi ? 1 : 0;
+  const int f = fused ? pw : -1;
+  if (pc == kPcJacobi) e_update_pc<T, kPcJacobi>(st, e, gr, f);
+  else e_update_pc<T, kPcNone>(st, e, gr, f);
 }
 
 template <typename T>
@@ -973,8 +858,8 @@ void e_finish(hipStream_t st, const Engine& e, int op, int expect, int mode, boo
   template void e_rhs<T>(hipStream_t, const Engine&, int, int);                        \
   template void e_pass<T>(hipStream_t, const Engine&, int, int);                       \
   template void e_resid<T>(hipStream_t, const Engine&, int, int, bool);                \
-  template void e_spmv<T>(hipStream_t, const Engine&, int, int);                       \
-  template void e_update<T>(hipStream_t, const Engine&, int, int);                     \
+  template void e_spmv<T>(hipStream_t, const Engine&, int, int, bool);                       \
+  template void e_update<T>(hipStream_t, const Engine&, int, int, bool);                     \
   template void e_apply<T>(hipStream_t, const Engine&, int);
 LPU_INST_E(float)
 LPU_INST_E(double)
