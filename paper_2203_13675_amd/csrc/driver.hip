@@ -67,7 +67,7 @@ static double now_ms() {
 // engine set-up
 // ---------------------------------------------------------------------------
 static void engine_free(Engine& e) {
-  void* ptrs[] = {e.desc, e.ms, e.tile_map, e.dtile_map, e.act, e.dact, e.mact, e.fcnt, e.gcnt, e.counts,
+  void* ptrs[] = {e.desc, e.ms, e.tile_map, e.dtile_map, e.act, e.dact, e.mact, e.fcnt, e.gcnt, e.eot, e.counts,
                   e.dx, e.dy, e.phi_prev, e.r64, e.U, e.V, e.aux, e.x[0], e.x[1], e.d[0],
                   e.d[1], e.r, e.s, e.q, e.b, e.t1, e.t2, e.iso, e.P};
   for (void* p : ptrs)
@@ -192,6 +192,7 @@ static int engine_setup(lp_unwrap_ctx* ctx, int n, const lpu_map* maps, int elem
     A((void**)&e.ms, sizeof(MapState) * n);
     A((void**)&e.tile_map, 4 * (size_t)tiles);
     A((void**)&e.dtile_map, 4 * (size_t)dtiles);
+    A((void**)&e.eot, sizeof(EoTile) * 2 * (size_t)std::max(dtiles, 1));
     A((void**)&e.act, 4 * (size_t)tiles);
     const long long dcap = (long long)dtiles + 8LL * (n + 1) * 256 + 64;
     A((void**)&e.dact, 4 * (size_t)(2 * dcap));
@@ -252,6 +253,51 @@ static int engine_setup(lp_unwrap_ctx* ctx, int n, const lpu_map* maps, int elem
   LPU_HIP_CHECK(ctx, hipMemcpyAsync(e.desc, hd.data(), sizeof(MapDesc) * n, hipMemcpyHostToDevice, st));
   LPU_HIP_CHECK(ctx, hipMemcpyAsync(e.tile_map, tm.data(), 4 * (size_t)tiles, hipMemcpyHostToDevice, st));
   LPU_HIP_CHECK(ctx, hipMemcpyAsync(e.dtile_map, dm.data(), 4 * (size_t)dtiles, hipMemcpyHostToDevice, st));
+  std::vector<EoTile> eo;
+  if (need_dct && dct_trows == 128 && dtiles > 0) {
+    // even/odd tile records for both stage parities
+    eo.resize(2 * (size_t)dtiles);
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int m = 0; m < n; ++m) {
+      const MapDesc& d = hd[m];
+      int stt = 0;
+      const DctTables* tM = get_dct_tables(ctx, d.M, &stt);
+      const DctTables* tN = tM ? get_dct_tables(ctx, d.N, &stt) : nullptr;
+      if (!tM || !tN) return stt ? stt : LPU_ERR_OOM;
+      const double l1M = (double)(2.0L - 2.0L * std::cos(pi / d.M));
+      const double l1N = (double)(2.0L - 2.0L * std::cos(pi / d.N));
+      for (int par = 0; par < 2; ++par) {
+        const DctTables* tk = par ? tM : tN;  // the contracted side's tables
+        const int R = par ? d.N : d.M, K = par ? d.M : d.N;
+        const int tiles_r = (R + 127) / 128;
+        for (int local = 0; local < d.ndt; ++local) {
+          EoTile& r = eo[(size_t)par * dtiles + d.dtile0 + local];
+          r.off = d.off;
+          r.tf[0] = tk->eo_h;
+          r.tf[1] = tk->eo_hi;
+          r.tf[2] = tk->eo_lo;
+          r.ti[0] = tk->eot_h;
+          r.ti[1] = tk->eot_hi;
+          r.ti[2] = tk->eot_lo;
+          r.lam_m = tM->lam_split;
+          r.lam_n = tN->lam_split;
+          r.m = m;
+          r.R = R;
+          r.K = K;
+          r.r0 = (local % tiles_r) * 128;
+          r.c0 = (local / tiles_r) * kDT;
+          r.local = local;
+          r.ndt = d.ndt;
+          r.gbd = d.gbd;
+          r.pad = 0;
+          r.lmin = (float)std::fmin(l1M, l1N);
+        }
+      }
+    }
+    LPU_HIP_CHECK(ctx, hipMemcpyAsync(e.eot, eo.data(), sizeof(EoTile) * dtiles, hipMemcpyHostToDevice, st));
+    LPU_HIP_CHECK(ctx, hipMemcpyAsync(e.eot + e.cap_dtiles, eo.data() + dtiles, sizeof(EoTile) * dtiles,
+                                      hipMemcpyHostToDevice, st));
+  }
   LPU_HIP_CHECK(ctx, hipStreamSynchronize(st));  // pageable sources
   return LPU_OK;
 }

@@ -51,6 +51,22 @@ struct DctTabDev {
   const double* lam_split;
 };
 
+// One tile of the even/odd DCT stages for one stage parity (rows of X are the
+// map's rows for parity 0, its columns for parity 1), with everything a block
+// reads to start the tile, so a tile costs one record load instead of a chain
+// of descriptor loads.
+struct EoTile {
+  long long off;          // element offset of the map
+  const uint16_t* tf[3];  // forward tables EO of the contracted side: fp16, bf16 hi, bf16 lo
+  const uint16_t* ti[3];  // inverse tables EOt: fp16, bf16 hi, bf16 lo
+  const double* lam_m;    // eigenvalues along M and along N, in split order
+  const double* lam_n;
+  int m, R, K, r0, c0;    // map, rows and contraction length at this parity, tile origin
+  int local, ndt, gbd;    // tile index within the map, the map's tile count, arrival group base
+  float lmin;             // smallest nonzero eigenvalue of the map's Laplacian
+  int pad;
+};
+
 struct MapDesc {
   int M, N;
   int th;                     // stencil tile height (rows)
@@ -101,6 +117,7 @@ struct Engine {
   int* mact = nullptr;       // active maps (sweep kernels)
   int* fcnt = nullptr;       // per-map arrival counters of the fused finishers (zero between launches)
   int* gcnt = nullptr;       // per-group arrival counters (groups of kArriveGroup tiles of one map)
+  EoTile* eot = nullptr;     // even/odd DCT tile records, [parity][global DCT tile]
   int* counts = nullptr;     // [0] active tiles, [1] DCT list (even stages), [2] active
                              // maps, [3] DCT list (odd stages)
   int* hcounts = nullptr;    // pinned

@@ -41,6 +41,8 @@ struct DArgs {
   int trows;  // output tile rows: 64 (dense kernels) or 128 (even/odd kernels)
   int cidx;   // counts[] slot holding the length of `dact`
   int *fcnt, *gcnt;  // arrival counters of the fused finisher
+  const EoTile* eot;  // even/odd tile records: [stage parity][global DCT tile]
+  long long eot_cap;
   int fin_mode;  // last stage of the even/odd kernels: 0, or the FinishMode of
                  // the fused finisher (the map's r^T s, beta and stop tests)
 };
@@ -305,31 +307,22 @@ __global__ void __launch_bounds__(256, 2) k_e_dct_eo(DArgs a) {
   for (int t_ = blockIdx.x; t_ < nact; t_ += gridDim.x) {
     const int g = a.dact[t_];
     if (g < 0) continue;  // padding slot of the XCD-ordered list
-    const DTile t = dtile(a, g);
-    if (!t.ok) continue;  // uniform over the block
-    const int R = t.R, n = t.K, h = n >> 1, c0 = t.c0;
-    const float* X = reinterpret_cast<const float*>(a.X) + t.off;
-    const uint16_t* X16 = reinterpret_cast<const uint16_t*>(a.X) + t.off;
-    float* Out = reinterpret_cast<float*>(a.Out) + t.off;
-    uint16_t* Out16 = reinterpret_cast<uint16_t*>(a.Out) + t.off;
-    const uint16_t* T0 = INV ? (SPLIT ? t.tab->eot_hi : t.tab->eot_h) : (SPLIT ? t.tab->eo_hi : t.tab->eo_h);
-    const uint16_t* T1 = INV ? t.tab->eot_lo : t.tab->eo_lo;
-    MapState& st = a.ms[t.m];
+    // the tile's record (one load); its first K step is fetched before the
+    // map's state is read, so the two round trips overlap
+    const EoTile& tt = a.eot[(size_t)(a.stage & 1) * a.eot_cap + g];
+    const int R = tt.R, n = tt.K, h = n >> 1, c0 = tt.c0, r0 = tt.r0, tm = tt.m;
+    const long long toff = tt.off;
+    const int t_local = tt.local, t_ndt = tt.ndt, t_gbd = tt.gbd;
+    const float t_lmin = tt.lmin;
+    const double* t_lam_m = tt.lam_m;
+    const double* t_lam_n = tt.lam_n;
+    const float* X = reinterpret_cast<const float*>(a.X) + toff;
+    const uint16_t* X16 = reinterpret_cast<const uint16_t*>(a.X) + toff;
+    float* Out = reinterpret_cast<float*>(a.Out) + toff;
+    uint16_t* Out16 = reinterpret_cast<uint16_t*>(a.Out) + toff;
+    const uint16_t* T0 = INV ? (SPLIT ? tt.ti[1] : tt.ti[0]) : (SPLIT ? tt.tf[1] : tt.tf[0]);
+    const uint16_t* T1 = INV ? tt.ti[2] : tt.tf[2];
     float xs = 1.0f, inv_xs = 1.0f, os = 1.0f;
-    if (!SPLIT) {
-      // Scaled fp16: power-of-two scales from bounds that hold before any
-      // value exists.  The transforms are orthonormal, so every stage output
-      // is bounded by the Frobenius norm of r (first forward stage; twice
-      // that after the even/odd fold) or of S ./ Lambda <= ||r|| / lambda_min
-      // (second forward stage and the first inverse stage).
-      const MapDesc& dm = a.desc[t.m];
-      const float nr = (float)sqrt(st.rr) * 1.0000001f;
-      const float lmin = (float)fmin(as_global(dm.tabM->lam)[1], as_global(dm.tabN->lam)[1]);
-      const float b01 = 2.0f * nr, b23 = nr / lmin * 1.0000001f;
-      xs = fp16_scale(a.stage <= 1 ? b01 : b23);
-      inv_xs = 1.0f / xs;
-      os = fp16_scale(a.stage == 0 ? b01 : b23);
-    }
     // register staging of one K step
     float4 sa[IN16 ? 1 : XP], sb[IN16 ? 1 : XP];
     u16x8 ha[IN16 ? XP : 1], hb[IN16 ? XP : 1];
@@ -337,7 +330,7 @@ __global__ void __launch_bounds__(256, 2) k_e_dct_eo(DArgs a) {
     auto fetch = [&](int k0) {
 #pragma unroll
       for (int p = 0; p < XP; ++p) {
-        const size_t ro = (size_t)(t.r0 + xr + (256 / TPR) * p) * n;
+        const size_t ro = (size_t)(r0 + xr + (256 / TPR) * p) * n;
         const int ka = k0 + xk, kb = INV ? h + k0 + xk : n - VPT - k0 - xk;
         if (IN16) {
           ha[p] = *reinterpret_cast<const u16x8*>(X16 + ro + ka);
@@ -425,7 +418,28 @@ __global__ void __launch_bounds__(256, 2) k_e_dct_eo(DArgs a) {
 #pragma unroll
       for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     const int nsteps = h / KS;
+    // the map's state and the first step's operands are requested together;
+    // the compiler barriers keep that order (it would otherwise sink the
+    // operand loads behind the state test's branch)
+    const int m_state = a.ms[tm].state;
+    const double m_rr = a.ms[tm].rr;
+    const int t_iso = a.desc[tm].use_iso;
+    __asm__ volatile("" ::: "memory");
     fetch(0);
+    __asm__ volatile("" ::: "memory");
+    if (m_state != a.expect) continue;  // uniform over the block
+    if (!SPLIT) {
+      // Scaled fp16: power-of-two scales from bounds that hold before any
+      // value exists.  The transforms are orthonormal, so every stage output
+      // is bounded by the Frobenius norm of r (first forward stage; twice
+      // that after the even/odd fold) or of S ./ Lambda <= ||r|| / lambda_min
+      // (second forward stage and the first inverse stage).
+      const float nr = (float)sqrt(m_rr) * 1.0000001f;
+      const float b01 = 2.0f * nr, b23 = nr / t_lmin * 1.0000001f;
+      xs = fp16_scale(a.stage <= 1 ? b01 : b23);
+      inv_xs = 1.0f / xs;
+      os = fp16_scale(a.stage == 0 ? b01 : b23);
+    }
     for (int s = 0; s < nsteps; ++s) {
       __syncthreads();  // readers of the previous step (or tile) are done
       stash();
@@ -468,11 +482,10 @@ __global__ void __launch_bounds__(256, 2) k_e_dct_eo(DArgs a) {
     }
     // epilogue: lane holds D[row 4*(lane/16) + e][col lane mod 16] of each 16x16 tile,
     // i.e. outputs (c, rb .. rb+3) with rb a multiple of 4
-    const MapDesc& d = a.desc[t.m];
-    const float* rv = reinterpret_cast<const float*>(a.rvec) + t.off;
-    const unsigned char* iso = (a.iso && d.use_iso) ? a.iso + t.off : nullptr;
-    const auto* lamMs = as_global(d.tabM->lam_split);
-    const auto* lamNs = as_global(d.tabN->lam_split);
+    const float* rv = reinterpret_cast<const float*>(a.rvec) + toff;
+    const unsigned char* iso = (a.iso && t_iso) ? a.iso + toff : nullptr;
+    const auto* lamMs = as_global(t_lam_m);
+    const auto* lamNs = as_global(t_lam_n);
     double part = 0.0;
     auto emit = [&](int c, int rb, const float (&y)[4]) {
       float v[4] = {y[0], y[1], y[2], y[3]};
@@ -515,7 +528,7 @@ __global__ void __launch_bounds__(256, 2) k_e_dct_eo(DArgs a) {
         for (int i = 0; i < 4; ++i) {
           const float y[4] = {acc[i][j][0] * inv_xs, acc[i][j][1] * inv_xs, acc[i][j][2] * inv_xs,
                               acc[i][j][3] * inv_xs};
-          emit(c, t.r0 + wr + 16 * i + 4 * kq, y);
+          emit(c, r0 + wr + 16 * i + 4 * kq, y);
         }
       }
     } else {
@@ -540,7 +553,7 @@ __global__ void __launch_bounds__(256, 2) k_e_dct_eo(DArgs a) {
                               (hf ? o[1] - acc[i][j][1] : acc[i][j][1] + o[1]) * inv_xs,
                               (hf ? o[2] - acc[i][j][2] : acc[i][j][2] + o[2]) * inv_xs,
                               (hf ? o[3] - acc[i][j][3] : acc[i][j][3] + o[3]) * inv_xs};
-          emit(hf ? n - 1 - c : c, t.r0 + wr + 16 * i + 4 * kq, y);
+          emit(hf ? n - 1 - c : c, r0 + wr + 16 * i + 4 * kq, y);
         }
       }
     }
@@ -548,10 +561,9 @@ __global__ void __launch_bounds__(256, 2) k_e_dct_eo(DArgs a) {
       double vv[1] = {part};
       block_sum<1>(vv, red);
       if (tid == 0) store_partial(a.P + 1 * a.pstride + g, vv[0]);
-      if (a.fin_mode && last_arrival(a.fcnt, a.gcnt, t.m, g - a.desc[t.m].dtile0,
-                                       a.desc[t.m].ndt, a.desc[t.m].gbd, &fflag)) {
-        finish_map(a.desc, a.ms, a.P, a.pstride, t.m, kFinTail, a.fin_mode, 0, 0, fred);
-        rearm(a.fcnt, t.m);
+      if (a.fin_mode && last_arrival(a.fcnt, a.gcnt, tm, t_local, t_ndt, t_gbd, &fflag)) {
+        finish_map(a.desc, a.ms, a.P, a.pstride, tm, kFinTail, a.fin_mode, 0, 0, fred);
+        rearm(a.fcnt, tm);
       }
     }
   }
@@ -653,6 +665,8 @@ void e_dct_stage(hipStream_t st, const Engine& e, int ndtiles, int stage, int ex
   DArgs a;
   a.fcnt = e.fcnt;
   a.gcnt = e.gcnt;
+  a.eot = e.eot;
+  a.eot_cap = e.cap_dtiles;
   // the finisher rides on the last stage of the even/odd kernels only
   a.fin_mode = (stage == 3 && kind >= 4) ? fin_mode : 0;
   a.desc = e.desc;
