@@ -204,12 +204,13 @@ def main():
     if a.fp64_compare and not a.profile:
         t0 = time.perf_counter()
         o64 = default_options(precision="fp64", k_max=a.outer, outer_tol=0.0)
+        it64 = 0
         for ps, ph in zip(psis, phis):
-            ctx.solve(ps, phi=ph, options=o64, **opts)
+            it64 += ctx.solve(ps, phi=ph, options=o64, **opts).stats["inner_iters_total"]
         torch.cuda.synchronize()
         t64 = time.perf_counter() - t0
         out["fp64_sequential"] = {"value": total_px / t64 / 1e6, "unit": "Mpixel/s",
-                                  "seconds": t64}
+                                  "seconds": t64, "pcg_iters": it64}
         out["speedup_vs_fp64_sequential"] = out["value"] / out["fp64_sequential"]["value"]
 
     if a.calib_copy > 0:

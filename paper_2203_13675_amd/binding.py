@@ -164,6 +164,18 @@ def default_options(**kw) -> LpuOptions:
     return o
 
 
+def paper_options(**kw) -> LpuOptions:
+    """Algorithm 1 with the stopping criteria of the paper's experiments (Section 3):
+    the inner test on the preconditioned residual with eps = 0.005, k_max = 500, outer
+    tolerance 1e-6 on the relative change, l_max = 2MN, FP64, starting from the phi the
+    caller passes (a seeded random field stands for the paper's random start).  Keyword
+    arguments override single fields."""
+    base = dict(stop_rule="paper", eps_cg=0.005, k_max=500, outer_tol=1e-6, l_max=0,
+                precision="fp64", use_phi0=1)
+    base.update(kw)
+    return default_options(**base)
+
+
 def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 

@@ -666,6 +666,9 @@ static int run_maps(lp_unwrap_ctx* ctx, int n, const lpu_map* maps, double p, do
     if (!mixed) {
       e_rhs<T>(st, e, nt, 0);
       e_pass<T>(st, e, nt, kPassX0Phi);
+      // the set-up kernels' own time (the PCG below starts with a synchronising
+      // state upload anyway)
+      LPU_HIP_CHECK(ctx, hipStreamSynchronize(st));
       setup_ms += now_ms() - ts;
       std::vector<double> tl(act.size(), tol);
       std::vector<long long> lm, pr;

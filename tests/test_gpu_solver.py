@@ -166,6 +166,37 @@ def test_fp64_paper_stop_rule_and_random_start(ctx, oracle):
     assert d <= max(1e-6, 50 * sens)
 
 
+@pytest.mark.parametrize("pc", ["none", "jacobi", "ilu0", "ic0", "ssor", "dct"])
+@pytest.mark.parametrize("M,N", [(40, 32), (72, 56)])
+def test_paper_faithful_mode(ctx, oracle, pc, M, N):
+    """The paper's experiment settings (Section 3): random start, inner test
+    eps = 0.005 on the preconditioned residual, k_max = 500, outer tolerance
+    1e-6, l_max = 2MN, FP64.  The outer loop stops after the same number of
+    iterations as the oracle running Algorithm 1 with the same settings."""
+    from paper_2203_13675_amd.binding import paper_options
+    psi, _ = synth.peaks_map(M, N, scale=3.0, sigma=0.3, seed=M + 7)
+    phi0 = synth.random_phi0(M, N, seed=M + 8)
+    ref, sens = oracle_sensitivity(oracle, psi, None, p=0.0, precond=pc, stop_rule="paper",
+                                   k_max=500, outer_tol=1e-6, phi0=phi0)
+    res = ctx.solve(dev(psi), p=0.0, preconditioner=pc, options=paper_options(),
+                    phi=dev(phi0))
+    d = maxdiff(host(res.phi), ref.phi)
+    print("paper mode", pc, M, N, "outer", res.stats["outer_iters"], ref.outer_iters,
+          "inner", res.stats["inner_iters_total"], sum(ref.inner_iters), "maxdiff", d,
+          "sensitivity", sens)
+    assert ref.converged and res.status == 0
+    k = res.stats["outer_iters"]
+    assert abs(k - ref.outer_iters) <= 1
+    # inner iterations over the outer iterations both ran (the relative change
+    # can cross 1e-6 one iteration apart under different rounding; unpreconditioned
+    # CG's crossing of eps^2 delta_0 moves by a few percent with the order of the
+    # FP64 dot products)
+    ref_inner = sum(ref.inner_iters[:k])
+    slack = max(2 * k, 0.05 * ref_inner) + (ref.inner_iters[-1] if k > ref.outer_iters else 0)
+    assert abs(res.stats["inner_iters_total"] - ref_inner) <= slack
+    assert d <= max(1e-6, 50 * sens)
+
+
 def test_fp64_hole_mask(ctx, oracle):
     M, N = 96, 80
     psi, _ = synth.gaussians_map(M, N, width=(10, 40), sigma=0.3, seed=9)
