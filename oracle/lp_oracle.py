@@ -16,7 +16,9 @@ unwrapping", arXiv 2203.13675) in plain, slow, vectorised numpy:
 * ``apply_A`` / ``rhs``   -- the two sides of Eq. (7).
 * ``Preconditioner``      -- the five M of Section 2.1's list (I, D, ILU(0),
                              IC(0), SOR read as SSOR) plus the DCT Poisson
-                             preconditioner (the unweighted Neumann Laplacian).
+                             preconditioner (the unweighted Neumann Laplacian),
+                             and ILU(0), IC(0) and SSOR of the matrix taken in
+                             red-black order (a change of M, not in the paper).
 * ``pcg``                 -- the inner loop of Algorithm 1 (Shewchuk's PCG with
                              periodic true-residual replacement).
 * ``unwrap``              -- Algorithm 1 (outer fixed-point loop).
@@ -59,7 +61,8 @@ import numpy as np
 TWO_PI = 2.0 * np.pi
 PIVOT_FLOOR = 1e-4
 
-PRECONDITIONERS = {"none": 0, "jacobi": 1, "ilu0": 2, "ic0": 3, "ssor": 4, "dct": 5}
+PRECONDITIONERS = {"none": 0, "jacobi": 1, "ilu0": 2, "ic0": 3, "ssor": 4, "dct": 5,
+                   "ilu0_rb": 6, "ic0_rb": 7, "ssor_rb": 8}
 
 # ---------------------------------------------------------------------------
 # native helper (generic CSR ILU(0)/IC(0)/SSOR)
@@ -229,6 +232,31 @@ def assemble_csr(U, V):
     return rowptr, c.astype(np.int32), np.ascontiguousarray(v, dtype=np.float64)
 
 
+def red_black_order(M: int, N: int) -> np.ndarray:
+    """Two-colour ordering of the grid: the pixels with i + j even ("red") first,
+    then those with i + j odd ("black"), each colour in row-major order.  Entry k
+    is the row-major pixel number i*N + j placed at position k."""
+    idx = np.arange(M * N).reshape(M, N)
+    red = (np.arange(M)[:, None] + np.arange(N)[None, :]) % 2 == 0
+    return np.concatenate([idx[red], idx[~red]]).astype(np.int64)
+
+
+def permute_csr(rowptr, col, a, perm):
+    """P A P^T in CSR with sorted columns, where row k of the result is row perm[k]
+    of A (and likewise for columns)."""
+    n = len(rowptr) - 1
+    inv = np.empty(n, dtype=np.int64)
+    inv[perm] = np.arange(n)
+    rows = np.repeat(np.arange(n), np.diff(rowptr))
+    r2, c2 = inv[rows], inv[np.asarray(col, dtype=np.int64)]
+    order = np.lexsort((c2, r2))
+    r2, c2, v2 = r2[order], c2[order], np.asarray(a)[order]
+    rp = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(rp, r2 + 1, 1)
+    return (np.cumsum(rp).astype(np.int32), c2.astype(np.int32),
+            np.ascontiguousarray(v2, dtype=np.float64))
+
+
 def isolated_pixels(U, V):
     """Pixels whose four edge weights are all zero (a zero row of A)."""
     return diag_A(U, V) == 0.0
@@ -275,15 +303,21 @@ class Preconditioner:
         if self.kind == "jacobi":
             d = diag_A(self.U, self.V)
             self.inv_diag = np.where(d > 0, 1.0 / np.where(d > 0, d, 1.0), 0.0)
-        elif self.kind in ("ilu0", "ic0", "ssor"):
+        elif self.kind in ("ilu0", "ic0", "ssor", "ilu0_rb", "ic0_rb", "ssor_rb"):
             rowptr, col, a = assemble_csr(self.U, self.V)
             # an isolated pixel's row is replaced by the identity row
             diag_pos = self._diag_positions(rowptr, col)
             a = a.copy()
             a[diag_pos[self.iso.ravel()]] = 1.0
+            self.base = self.kind[:-3] if self.kind.endswith("_rb") else self.kind
+            # red-black variants: the same factorisation of P A P^T
+            self.perm = red_black_order(M, N) if self.kind.endswith("_rb") else None
+            if self.perm is not None:
+                rowptr, col, a = permute_csr(rowptr, col, a, self.perm)
+                diag_pos = self._diag_positions(rowptr, col)
             self.rowptr, self.col, self.a = rowptr, col, a
             self.diag_pos = diag_pos
-            if self.kind in ("ilu0", "ic0"):
+            if self.base in ("ilu0", "ic0"):
                 self._factor()
         elif self.kind == "dct":
             self.CM = dct_matrix(M)
@@ -306,7 +340,7 @@ class Preconditioner:
         lib = _native()
         n = len(self.rowptr) - 1
         out = np.empty_like(self.a)
-        f = lib.orc_ilu0 if self.kind == "ilu0" else lib.orc_ic0
+        f = lib.orc_ilu0 if self.base == "ilu0" else lib.orc_ic0
         rc = f(n, self.rowptr, self.col, self.a, PIVOT_FLOOR, out)
         if rc < 0:
             raise RuntimeError("row %d has no diagonal entry" % (-rc - 1))
@@ -317,8 +351,12 @@ class Preconditioner:
         """Diagonal of the no-fill factor as a (M, N) array (ILU: U's diagonal,
         IC: squared diagonal of L); both equal the D-ILU pivots for Eq. (7)'s A."""
         p = self.factor[self.diag_pos]
-        if self.kind == "ic0":
+        if self.base == "ic0":
             p = p * p
+        if self.perm is not None:
+            q = np.empty_like(p)
+            q[self.perm] = p
+            p = q
         return p.reshape(self.shape)
 
     def apply(self, r: np.ndarray) -> np.ndarray:
@@ -336,14 +374,21 @@ class Preconditioner:
         else:
             lib = _native()
             n = r.size
-            rr = np.ascontiguousarray(r.ravel())
+            rr = r.ravel()
+            if self.perm is not None:
+                rr = rr[self.perm]
+            rr = np.ascontiguousarray(rr)
             s = np.empty(n)
-            if k == "ilu0":
+            if self.base == "ilu0":
                 lib.orc_lu_solve(n, self.rowptr, self.col, self.factor, rr, s)
-            elif k == "ic0":
+            elif self.base == "ic0":
                 lib.orc_llt_solve(n, self.rowptr, self.col, self.factor, rr, s)
             else:
                 lib.orc_ssor_solve(n, self.rowptr, self.col, self.a, float(self.omega), rr, s)
+            if self.perm is not None:
+                t = np.empty(n)
+                t[self.perm] = s
+                s = t
             s = s.reshape(r.shape)
         return np.where(self.keep, s, 0.0)
 

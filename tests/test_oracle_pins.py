@@ -379,6 +379,55 @@ def pin_incomplete_factorizations(O):
     return bool(ok)
 
 
+def pin_red_black_factorizations(O):
+    """ILU(0), IC(0) and SSOR of the matrix taken in red-black order (i + j even
+    first): the ordering puts every even-parity pixel before every odd one and
+    keeps row-major order inside each colour; the no-fill factor of P A P^T
+    (brute-force dense elimination on the permuted pattern) reproduces P A P^T on
+    its pattern and is what the oracle applies; its pivots have the closed form
+    of a two-colour ordering (even pixels: the diagonal; odd pixels: the diagonal
+    minus the squared couplings to their even neighbours over those neighbours'
+    diagonals); IC(0) gives the same preconditioner; SSOR matches its matrix
+    formula in the permuted order."""
+    rng = np.random.default_rng(19)
+    M, N = 5, 7
+    U, V = random_weights(M, N, rng)
+    rowptr, col, a = O.assemble_csr(U, V)
+    A = scipy.sparse.csr_matrix((a, col, rowptr), shape=(M * N, M * N)).toarray()
+    P = _dense_pattern(M, N)
+    r = rng.normal(size=(M, N))
+    perm = np.asarray(O.red_black_order(M, N))
+    ii, jj = perm // N, perm % N
+    nred = (M * N + 1) // 2
+    ok = sorted(perm.tolist()) == list(range(M * N))
+    ok &= bool(np.all((ii[:nred] + jj[:nred]) % 2 == 0) and np.all((ii[nred:] + jj[nred:]) % 2 == 1))
+    ok &= bool(np.all(np.diff(perm[:nred]) > 0) and np.all(np.diff(perm[nred:]) > 0))
+    Ap, Pp = A[np.ix_(perm, perm)], P[np.ix_(perm, perm)]
+    L, Uu = _dense_ilu0(Ap, Pp)
+    ok &= np.allclose((L @ Uu)[Pp], Ap[Pp], atol=1e-13)
+    s_ilu = O.Preconditioner("ilu0_rb", U, V).apply(r)
+    want = np.empty(M * N)
+    want[perm] = np.linalg.solve(L @ Uu, r.ravel()[perm])
+    ok &= np.allclose(s_ilu.ravel(), want, atol=1e-12)
+    d = np.diag(A)
+    piv = d.copy()
+    for q in range(M * N):
+        if (q // N + q % N) % 2 == 1:
+            nb = [t for t in range(M * N) if t != q and A[q, t] != 0.0]
+            piv[q] = d[q] - sum(A[q, t] ** 2 / d[t] for t in nb)
+    ok &= np.allclose(O.Preconditioner("ilu0_rb", U, V).pivots().ravel(), piv, atol=1e-13)
+    s_ic = O.Preconditioner("ic0_rb", U, V).apply(r)
+    ok &= np.allclose(s_ilu, s_ic, atol=1e-12)
+    Dd = np.diag(np.diag(Ap))
+    Ls = np.tril(Ap, -1)
+    for w in (1.0, 1.4):
+        Ms = (Dd / w + Ls) @ np.linalg.inv(Dd / w) @ (Dd / w + Ls.T) / (2.0 - w)
+        s = O.Preconditioner("ssor_rb", U, V, omega=w).apply(r)
+        want[perm] = np.linalg.solve(Ms, r.ravel()[perm])
+        ok &= np.allclose(s.ravel(), want, atol=1e-12)
+    return bool(ok)
+
+
 def pin_monotone_descent(O):
     """With exact inner solves the outer loop is majorise-minimise for the
     tau-regularised energy, so the energy never increases (p = 0 and p = 1)."""
@@ -418,7 +467,8 @@ def pin_normalized_error(O):
 PINS = [pin_wrap_range_and_ties, pin_wrapped_differences, pin_weights_hand_values,
         pin_normal_equations, pin_gradient_of_energy, pin_laplacian_properties,
         pin_dense_lstsq, pin_scipy_cg, pin_exact_recovery, pin_p2_dct_one_step,
-        pin_dct_against_library, pin_incomplete_factorizations, pin_monotone_descent,
+        pin_dct_against_library, pin_incomplete_factorizations, pin_red_black_factorizations,
+        pin_monotone_descent,
         pin_cg_finite_termination, pin_normalized_error]
 
 
@@ -526,6 +576,13 @@ def pin_laplacian_properties_matrix_free(O):
 
 def test_matrix_free_properties(oracle):
     assert pin_laplacian_properties_matrix_free(oracle)
+
+
+def test_mutation_red_black_order(oracle, monkeypatch):
+    """A two-colour ordering that keeps the colours interleaved (the natural order)
+    is caught."""
+    _mutant(oracle, monkeypatch, "red_black_order", lambda M, N: np.arange(M * N))
+    assert not pin_red_black_factorizations(oracle)
 
 
 def test_mutation_dct_unnormalised(oracle, monkeypatch):
