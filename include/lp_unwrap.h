@@ -64,7 +64,14 @@ enum lpu_preconditioner {
     LPU_PC_IC0 = 3,     /* incomplete Cholesky, no fill-in; for this symmetric
                            five-point matrix it equals ILU(0)                    */
     LPU_PC_SSOR = 4,    /* symmetric SOR with relaxation ssor_omega              */
-    LPU_PC_DCT = 5      /* DCT-II/III Poisson solve, zero mode dropped           */
+    LPU_PC_DCT = 5,     /* DCT-II/III Poisson solve, zero mode dropped           */
+    /* The same three factorisations of the matrix taken in two-colour (red-black)
+       order: pixels with i + j even first, then odd, row-major within a colour.
+       A different M from the natural-order ones (not in the paper); both of its
+       triangular solves are one parallel pass each.                            */
+    LPU_PC_ILU0_RB = 6, /* ILU(0) in two-colour order                            */
+    LPU_PC_IC0_RB = 7,  /* IC(0) in two-colour order (equals LPU_PC_ILU0_RB)      */
+    LPU_PC_SSOR_RB = 8  /* SSOR(ssor_omega) in two-colour order                  */
 };
 
 enum lpu_stop_rule {
@@ -225,7 +232,8 @@ enum lpu_kernel_class {
     LPU_KC_DCT = 4,      /* one DCT contraction stage                      */
     LPU_KC_SWEEP = 5,    /* ILU/IC/SSOR forward+backward sweeps            */
     LPU_KC_SETUP = 6,    /* weights, b, preconditioner set-up, refinement  */
-    LPU_KC_COUNT = 7
+    LPU_KC_TWOCOLOR = 7, /* the two passes of a two-colour preconditioner  */
+    LPU_KC_COUNT = 8
 };
 
 /* Time every launch of the kernel classes whose bit (1 << class) is set in

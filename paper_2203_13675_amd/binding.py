@@ -26,7 +26,8 @@ ERR_HIP = -3
 ERR_NONFINITE = -4
 ERR_BREAKDOWN = -5
 
-PRECONDITIONERS = {"none": 0, "jacobi": 1, "ilu0": 2, "ic0": 3, "ssor": 4, "dct": 5}
+PRECONDITIONERS = {"none": 0, "jacobi": 1, "ilu0": 2, "ic0": 3, "ssor": 4, "dct": 5,
+                   "ilu0_rb": 6, "ic0_rb": 7, "ssor_rb": 8}
 STOP_RULES = {"relres": 0, "paper": 1}
 PRECISIONS = {"fp64": 0, "mixed": 1}
 DCT_MODES = {"fp32": 0, "split_bf16": 1, "fp16_scaled": 2}
@@ -74,7 +75,7 @@ EXPORTED = ["lpu_default_options", "lp_unwrap_create", "lp_unwrap_destroy", "lp_
 
 # kernel classes of the instrumentation (lpu_kernel_class)
 KERNEL_CLASSES = {"spmv": 0, "update": 1, "confirm": 2, "init": 3, "dct": 4, "sweep": 5,
-                  "setup": 6}
+                  "setup": 6, "twocolor": 7}
 
 
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:

@@ -91,7 +91,7 @@ int check_options(lp_unwrap_ctx* ctx, int M, int N, int pc, const lpu_options& o
   if (!(o.refine_eta > 0.0 && o.refine_eta < 1.0))
     return set_error(ctx, LPU_ERR_INVALID_ARG, "refine_eta outside (0, 1)");
   if (o.max_refine < 1) return set_error(ctx, LPU_ERR_INVALID_ARG, "max_refine < 1");
-  if (pc < LPU_PC_NONE || pc > LPU_PC_DCT)
+  if (pc < LPU_PC_NONE || pc > LPU_PC_SSOR_RB)
     return set_error(ctx, LPU_ERR_INVALID_ARG, "unknown preconditioner");
   if ((pc == LPU_PC_ILU0 || pc == LPU_PC_IC0 || pc == LPU_PC_SSOR) && N > 4096)
     return set_error(ctx, LPU_ERR_INVALID_ARG, "sweep preconditioners support N <= 4096");

@@ -37,6 +37,9 @@ void e_dct_stage(hipStream_t st, const Engine& e, int ndtiles, int stage, int ex
 int egrid(const Engine& e, int ntiles);
 int dct_grid_for(const Engine& e, int ndtiles);
 template <typename T> void e_pivots(hipStream_t, const Engine&, int, int, bool, double);
+template <typename T> void e_tc_pivots(hipStream_t, const Engine&, int, bool, double);
+template <typename T>
+void e_twocolor(hipStream_t, const Engine&, int, int, bool, double, int);
 template <typename T>
 void e_sweep(hipStream_t, const Engine&, int, int, int, bool, double, const void*, void*, void*);
 
@@ -409,12 +412,18 @@ struct Pcg {
 
   // Preconditioner apply s = M^-1 r for the maps in state `expect`, then the
   // per-map finisher of r^T s with FinishMode `mode` (inside the last DCT
-  // stage for the even/odd kernels, as a launch of its own otherwise).
-  void tail(hipStream_t st, int ndt, int nmaps, int expect, int mode) {
+  // stage for the even/odd kernels and the second two-colour pass, as a
+  // launch of its own otherwise).
+  void tail(hipStream_t st, int nt, int ndt, int nmaps, int expect, int mode) {
     Engine& e = ctx->eng;
     KTimer& kt = ctx->kt;
     bool fused = false;
-    if (pc == kPcDct) {
+    if (two_colour(pc)) {
+      const int ev = kt.begin(LPU_KC_TWOCOLOR, st);
+      e_twocolor<T>(st, e, nt, expect, pc == kPcSsorRb, omega, mode);
+      kt.end(ev, LPU_KC_TWOCOLOR, st);
+      fused = true;
+    } else if (pc == kPcDct) {
       const void* in[4] = {e.r, e.t1, e.t2, e.t1};
       void* out[4] = {e.t1, e.t2, e.t1, e.s};
       fused = dct_kind >= 4;
@@ -449,7 +458,7 @@ struct Pcg {
     ev = kt.begin(LPU_KC_UPDATE, st);
     e_update<T>(st, e, nt, pc, true);
     kt.end(ev, LPU_KC_UPDATE, st);
-    if (!pointwise()) tail(st, nd, nm, kRun, kFinishIter);
+    if (!pointwise()) tail(st, nt, nd, nm, kRun, kFinishIter);
   }
 
   // Issue K iterations: as K launches of a captured graph of the body (one
@@ -521,7 +530,7 @@ struct Pcg {
     kt.end(ev, LPU_KC_INIT, st);
     fin(st, kFinInitH, kRun);
     if (!pw) {
-      tail(st, nd, (int)set.size(), kInitPc, kFinishInit);
+      tail(st, nt, nd, (int)set.size(), kInitPc, kFinishInit);
     }
     long long K = 4;
     const long long Kcap = std::max(2, ctx->tune.max_batch_iters);
@@ -534,7 +543,7 @@ struct Pcg {
       kt.end(ev, LPU_KC_CONFIRM, st);
       fin(st, kFinConfirmH, kConfirm);
       if (!pw) {
-        tail(st, nd, (int)set.size(), kConfirmPc, kFinishConfirm);
+        tail(st, nt, nd, (int)set.size(), kConfirmPc, kFinishConfirm);
       }
       if ((rc = read_states(ctx))) return rc;
       std::vector<int> still;
@@ -643,6 +652,10 @@ static int run_maps(lp_unwrap_ctx* ctx, int n, const lpu_map* maps, double p, do
         const double bytes = io + 2.0 * half * Nn * Nn * tab + 2.0 * half * Mm * Mm * tab + px * el;
         kt.credit(LPU_KC_DCT, 4 * s.nfinish, s.nfinish * bytes,
                   s.nfinish * 4.0 * px * (Mm + Nn) * prod * half);
+      } else if (two_colour(pc)) {
+        // per application, two passes: read r, pivots, U, V (+ s on half the
+        // pixels in the second) and write s on half the pixels each
+        kt.credit(LPU_KC_TWOCOLOR, 2 * s.nfinish, s.nfinish * px * el * 10.0, s.nfinish * px * 30.0);
       } else if (!pcg.pointwise()) {
         kt.credit(LPU_KC_SWEEP, s.nfinish, s.nfinish * px * el * 10.0, s.nfinish * px * 14.0);
       }
@@ -662,6 +675,8 @@ static int run_maps(lp_unwrap_ctx* ctx, int n, const lpu_map* maps, double p, do
     if (need_diag || any_mask) e_diag<T>(st, e, nt, need_diag);
     if (pc == kPcIlu || pc == kPcIc || pc == kPcSsor)
       e_pivots<T>(st, e, (int)act.size(), e.max_n, pc == kPcSsor, o.ssor_omega);
+    else if (two_colour(pc))
+      e_tc_pivots<T>(st, e, nt, pc == kPcSsorRb, o.ssor_omega);
     kt.end(ev, LPU_KC_SETUP, st);
     if (!mixed) {
       e_rhs<T>(st, e, nt, 0);
@@ -928,6 +943,12 @@ int step_precond(lp_unwrap_ctx* ctx, int M, int N, int pc, int dct_mode, double 
       e_dct_stage(st, e, e.total_dtiles, k, kRun, kind, in[k], out[k], e.r, 0);
       ctx->kt.end(ev, LPU_KC_DCT, st);
     }
+    if ((rc = copy_in(ctx, s, e.s, b))) return rc;
+  } else if (two_colour(pc)) {
+    e_tc_pivots<T>(st, e, e.total_tiles, pc == kPcSsorRb, omega);
+    const int ev = ctx->kt.begin(LPU_KC_TWOCOLOR, st);
+    e_twocolor<T>(st, e, e.total_tiles, kRun, pc == kPcSsorRb, omega, 0);
+    ctx->kt.end(ev, LPU_KC_TWOCOLOR, st);
     if ((rc = copy_in(ctx, s, e.s, b))) return rc;
   } else {
     e_pivots<T>(st, e, 1, N, pc == kPcSsor, omega);

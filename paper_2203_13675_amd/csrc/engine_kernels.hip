@@ -274,6 +274,8 @@ struct EArgs {
   const unsigned char* iso;
   int *fcnt, *gcnt;  // arrival counters of the finisher fused into the tile kernel
   int fuse_pw;  // -1: no fused finisher; else its pointwise-preconditioner flag
+  int expect;   // two-colour preconditioner: state of the maps it applies to
+  int fin_mode;  // two-colour preconditioner: FinishMode of its fused finisher (0: none)
 };
 
 #define TILE_LOOP(A)                                                  \
@@ -678,6 +680,124 @@ __global__ void __launch_bounds__(64) k_e_update(EArgs A) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Two-colour ILU(0) = IC(0) and SSOR of Eq. (7)'s matrix (a GPU-parallel
+// change of M; the paper's sweeps use the natural order).  Pixel (i, j) is
+// "even" when i + j is even.  With the even pixels ordered first the matrix is
+// [[D_e, -B], [-B^T, D_o]]: no two pixels of one colour are coupled, so the
+// no-fill factorisation keeps the even diagonal as pivots and gives the odd
+// pivots p_o = a_oo - sum over even neighbours e of a_oe^2 / a_ee (SSOR: every
+// pivot a / omega).  M = (P + L) P^-1 (P + L^T) (over 2 - omega for SSOR) is
+// applied in two passes, c = 2 - omega for SSOR and 1 otherwise:
+//   odd pixels:  s_o = c (r_o + sum_e w_oe r_e / p_e) / p_o   (forward solve)
+//   even pixels: s_e = (c r_e + sum_o w_eo s_o) / p_e         (backward solve)
+// Each pass is a stencil march of Eq. (7) with an operand that is zero on the
+// pixels it writes, so the neighbour sum is -(A x) there; the first pass only
+// writes odd pixels and the second only even ones, and each reads s only on
+// the colour it does not write.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(64) k_e_tc_pivots(EArgs A, int ssor, double omega) {
+  TILE_LOOP(A) {
+    const int g = A.act[t_];
+    const TilePos tp = tile_pos(A.desc, A.tile_map, g);
+    const T* U = cvec<T>(A.U, tp.off);
+    const T* V = cvec<T>(A.V, tp.off);
+    T* piv = vec<T>(A.aux, tp.off);
+    unsigned char* iso = const_cast<unsigned char*>(A.iso) + tp.off;
+    const int M = tp.M, N = tp.N;
+    auto diag = [&](int i, int j) {
+      return ldz(U, i, j - 1, M, N) + ldz(U, i, j, M, N) + ldz(V, i - 1, j, M, N) + ldz(V, i, j, M, N);
+    };
+    march_points(tp, [&](int i, int j) {
+      const size_t p = (size_t)i * N + j;
+      const T d = diag(i, j);
+      iso[p] = d == T(0) ? 1 : 0;
+      T q = d;
+      if (d == T(0)) {
+        q = T(1);  // isolated pixel: identity row, output forced to zero
+      } else if (ssor) {
+        q = d / (T)omega;
+      } else if ((i + j) & 1) {
+        // couplings to the four (even) neighbours and their diagonals
+        const T w[4] = {ldz(U, i, j - 1, M, N), ldz(U, i, j, M, N), ldz(V, i - 1, j, M, N),
+                        ldz(V, i, j, M, N)};
+        const int ni[4] = {i, i, i - 1, i + 1}, nj[4] = {j - 1, j + 1, j, j};
+        T sub = T(0);
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          if (w[k] != T(0)) sub += w[k] * w[k] / diag(ni[k], nj[k]);
+        q = d - sub;
+        if (q < T(1e-4) * d) q = d;  // the pivot floor of the natural-order factorisation
+      }
+      piv[p] = q;
+    });
+  }
+}
+
+template <typename T, int PASS, int TH>
+__global__ void __launch_bounds__(64) k_e_twocolor(EArgs A, T c) {
+  __shared__ double fred[3];
+  __shared__ int fflag;
+  TILE_LOOP(A) {
+    const int g = A.act[t_];
+    const TilePos tp = tile_pos(A.desc, A.tile_map, g);
+    if (A.ms[tp.m].state != A.expect) continue;
+    const T* U = cvec<T>(A.U, tp.off);
+    const T* V = cvec<T>(A.V, tp.off);
+    const T* piv = cvec<T>(A.aux, tp.off);
+    const T* r = cvec<T>(A.r, tp.off);
+    T* s = vec<T>(A.s, tp.off);
+    const unsigned char* iso = A.iso + tp.off;
+    const int M = tp.M, N = tp.N;
+    double part = 0.0;
+    march_tile<TH, T>(
+        tp, U, V,
+        [&](int i, int j) {
+          bool ok;
+          const size_t p = clamp_at(i, j, M, N, ok);
+          const bool even = ((i + j) & 1) == 0;
+          R3<T> v;  // pass 0: r and the pivot on even pixels; pass 1: s on odd pixels
+          if (PASS == 0) {
+            const T r0 = r[p], p0 = piv[p];
+            v.s = ok && even ? r0 : T(0);
+            v.w = p0;
+          } else {
+            const T s0 = s[p];
+            v.s = ok && !even ? s0 : T(0);
+            v.w = T(1);
+          }
+          v.d = T(0);
+          return v;
+        },
+        [&](const R3<T>& v) { return PASS == 0 ? v.s / v.w : v.s; },
+        [&](int i, int j, T xv, T ax) {
+          const size_t p = (size_t)i * N + j;
+          const bool even = ((i + j) & 1) == 0;
+          if (PASS == 0) {
+            if (!even) s[p] = iso[p] ? T(0) : c * (r[p] - ax) / piv[p];
+          } else {
+            const T rv = r[p];
+            T sv = xv;
+            if (even) {
+              sv = iso[p] ? T(0) : (c * rv - ax) / piv[p];
+              s[p] = sv;
+            }
+            part += (double)rv * (double)sv;
+          }
+        });
+    if (PASS == 1) {
+      part = wave_sum(part);
+      if (lane_id() == 0) store_partial(A.P + 1 * A.pstride + g, part);
+      const MapDesc& dm = A.desc[tp.m];
+      if (A.fin_mode && last_arrival(A.fcnt, A.gcnt, tp.m, g - dm.tile0, dm.ntiles, dm.gb, &fflag)) {
+        finish_map(A.desc, A.ms, A.P, A.pstride, tp.m, kFinTailS, A.fin_mode, 0, 0, fred);
+        rearm(A.fcnt, tp.m);
+      }
+    }
+  }
+}
+
 // y = A x for the step entry point (x in A.s, y in A.q)
 template <typename T>
 __global__ void __launch_bounds__(64) k_e_apply(EArgs A) {
@@ -749,6 +869,8 @@ EArgs make_args(const Engine& e) {
   a.fcnt = e.fcnt;
   a.gcnt = e.gcnt;
   a.fuse_pw = -1;
+  a.expect = kRun;
+  a.fin_mode = 0;
   return a;
 }
 
@@ -842,6 +964,37 @@ void e_update(hipStream_t st, const Engine& e, int ntiles, int pc, bool fused) {
 }
 
 template <typename T>
+void e_tc_pivots(hipStream_t st, const Engine& e, int ntiles, bool ssor, double omega) {
+  hipLaunchKernelGGL(k_e_tc_pivots<T>, dim3(egrid(e, ntiles)), dim3(64), 0, st, make_args(e),
+                     ssor ? 1 : 0, omega);
+}
+
+template <typename T, int PASS>
+static void e_twocolor_pass(hipStream_t st, const Engine& e, int gr, const EArgs& a, T c) {
+  switch (e.th) {
+    case 4: hipLaunchKernelGGL((k_e_twocolor<T, PASS, 4>), dim3(gr), dim3(64), 0, st, a, c); break;
+    case 8: hipLaunchKernelGGL((k_e_twocolor<T, PASS, 8>), dim3(gr), dim3(64), 0, st, a, c); break;
+    case 16: hipLaunchKernelGGL((k_e_twocolor<T, PASS, 16>), dim3(gr), dim3(64), 0, st, a, c); break;
+    case 32: hipLaunchKernelGGL((k_e_twocolor<T, PASS, 32>), dim3(gr), dim3(64), 0, st, a, c); break;
+    default: hipLaunchKernelGGL((k_e_twocolor<T, PASS, 0>), dim3(gr), dim3(64), 0, st, a, c); break;
+  }
+}
+
+// s = M^-1 r of the two-colour preconditioner for the maps in state `expect`;
+// fin_mode != 0 runs the per-map finisher of r^T s at the end of the second pass
+template <typename T>
+void e_twocolor(hipStream_t st, const Engine& e, int ntiles, int expect, bool ssor, double omega,
+                int fin_mode) {
+  const int gr = egrid(e, ntiles);
+  EArgs a = make_args(e);
+  a.expect = expect;
+  const T c = ssor ? (T)(2.0 - omega) : T(1);
+  e_twocolor_pass<T, 0>(st, e, gr, a, c);
+  a.fin_mode = fin_mode;
+  e_twocolor_pass<T, 1>(st, e, gr, a, c);
+}
+
+template <typename T>
 void e_apply(hipStream_t st, const Engine& e, int ntiles) {
   hipLaunchKernelGGL(k_e_apply<T>, dim3(egrid(e, ntiles)), dim3(64), 0, st, make_args(e));
 }
@@ -860,7 +1013,9 @@ void e_finish(hipStream_t st, const Engine& e, int op, int expect, int mode, boo
   template void e_resid<T>(hipStream_t, const Engine&, int, int, bool);                \
   template void e_spmv<T>(hipStream_t, const Engine&, int, int, bool);                       \
   template void e_update<T>(hipStream_t, const Engine&, int, int, bool);                     \
-  template void e_apply<T>(hipStream_t, const Engine&, int);
+  template void e_apply<T>(hipStream_t, const Engine&, int);                            \
+  template void e_tc_pivots<T>(hipStream_t, const Engine&, int, bool, double);         \
+  template void e_twocolor<T>(hipStream_t, const Engine&, int, int, bool, double, int);
 LPU_INST_E(float)
 LPU_INST_E(double)
 

@@ -16,7 +16,8 @@ enum FinOp : int {
   kFinUpdate = 2,   // slots 0,1: r.r, r.s
   kFinConfirm = 3,  // slots 0,1: r.r, r.s
   kFinTail = 4,     // slot 1 over DCT tiles (or one sweep partial): r.s
-  kFinSum2 = 5      // slots 0,1 over stencil tiles -> rr, bb (no state change)
+  kFinSum2 = 5,     // slots 0,1 over stencil tiles -> rr, bb (no state change)
+  kFinTailS = 6     // slot 1 over stencil tiles (two-colour preconditioners): r.s
 };
 
 __device__ inline void map_finish(MapState& s, int mode, double rs) {
@@ -130,6 +131,11 @@ __device__ inline void finish_map(const MapDesc* __restrict__ desc, MapState* ms
     double w[1];
     fin_sums<1>(P, pstride, d.dtile0, tail_single ? 1 : d.ndt, sl, w, smem);
     v[0] = w[0];
+  } else if (op == kFinTailS) {
+    const int sl[1] = {1};
+    double w[1];
+    fin_sums<1>(P, pstride, d.tile0, d.ntiles, sl, w, smem);
+    v[0] = w[0];
   } else {
     const int sl[2] = {0, 1};
     double w[2];
@@ -179,6 +185,7 @@ __device__ inline void finish_map(const MapDesc* __restrict__ desc, MapState* ms
       else s.state = kConfirmPc;
       break;
     case kFinTail:
+    case kFinTailS:
       s.rs = v[0];
       s.amax[1] = s.amax[2] = s.amax[3] = 0.0f;  // scaled-fp16 maxima of this application
       map_finish(s, mode, v[0]);

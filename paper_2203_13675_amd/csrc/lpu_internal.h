@@ -34,7 +34,10 @@ enum CgState : int {
 // How a finisher completes a PCG step.
 enum FinishMode : int { kFinishNone = 0, kFinishInit = 1, kFinishIter = 2, kFinishConfirm = 3 };
 
-enum PcKind : int { kPcNone = 0, kPcJacobi = 1, kPcIlu = 2, kPcIc = 3, kPcSsor = 4, kPcDct = 5 };
+enum PcKind : int { kPcNone = 0, kPcJacobi = 1, kPcIlu = 2, kPcIc = 3, kPcSsor = 4, kPcDct = 5,
+                    kPcIluRb = 6, kPcIcRb = 7, kPcSsorRb = 8 };
+// two-colour (red-black) ordered factorisations
+inline bool two_colour(int pc) { return pc == kPcIluRb || pc == kPcIcRb || pc == kPcSsorRb; }
 
 // DCT tables for one size n, in every arithmetic the kernels use.
 struct DctTables {

@@ -55,7 +55,7 @@ def stand_in(M: int, N: int, seed: int):
 def run(scales=None, pcs=None, precision="fp64", log=print):
     import torch
     from paper_2203_13675_amd.binding import Context, paper_options
-    pcs = pcs or PAPER_PCS + ["dct"]
+    pcs = pcs or PAPER_PCS + ["dct", "ilu0_rb", "ssor_rb"]
     rows = []
     ctx = Context(0)
     dev = torch.device("cuda:0")

@@ -69,7 +69,7 @@ def relres_bound(precision):
 # 1024 x 1024 peaks (+-60 rad, noise 0.5 rad): every preconditioner, p = 0, 1
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-@pytest.mark.parametrize("pc", ["none", "jacobi", "ilu0", "ssor", "dct"])
+@pytest.mark.parametrize("pc", ["none", "jacobi", "ilu0", "ssor", "dct", "ilu0_rb", "ssor_rb"])
 @pytest.mark.parametrize("p", [0.0, 1.0])
 def test_peaks1024_system_residual(ctx, oracle, p, pc, precision):
     psi, mask, _ = synth.workload("peaks1024")

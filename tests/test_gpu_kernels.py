@@ -145,12 +145,13 @@ def _precond_case(oracle, M, N, seed, hole):
 PC_SIZES = [(64, 64), (37, 53), (130, 77), (1, 40), (40, 1), (96, 160)]
 
 
-@pytest.mark.parametrize("pc", ["none", "jacobi", "ilu0", "ic0", "ssor", "dct"])
+@pytest.mark.parametrize("pc", ["none", "jacobi", "ilu0", "ic0", "ssor", "dct",
+                                "ilu0_rb", "ic0_rb", "ssor_rb"])
 @pytest.mark.parametrize("M,N", PC_SIZES)
 @pytest.mark.parametrize("hole", [False, True])
 def test_precond_fp64(ctx, oracle, pc, M, N, hole):
     U, V, r = _precond_case(oracle, M, N, 21, hole)
-    for omega in ((1.0, 1.5) if pc == "ssor" else (1.0,)):
+    for omega in ((1.0, 1.5) if pc in ("ssor", "ssor_rb") else (1.0,)):
         ref = oracle.Preconditioner(pc, U, V, omega=omega).apply(r)
         s = host(ctx.precond_apply(dev(U), dev(V), dev(r), pc, precision="fp64", omega=omega))
         scale = np.abs(ref).max() + 1e-300
@@ -161,7 +162,10 @@ def test_precond_fp64(ctx, oracle, pc, M, N, hole):
                                          ("ilu0", "fp32", 2e-4), ("ic0", "fp32", 2e-4),
                                          ("ssor", "fp32", 2e-4), ("dct", "fp32", 1e-4),
                                          ("dct", "split_bf16", 2e-4),
-                                         ("dct", "fp16_scaled", 1e-2)])
+                                         ("dct", "fp16_scaled", 1e-2),
+                                         # two explicit passes of a few FP32 terms each
+                                         ("ilu0_rb", "fp32", 2e-5), ("ic0_rb", "fp32", 2e-5),
+                                         ("ssor_rb", "fp32", 2e-5)])
 @pytest.mark.parametrize("M,N", PC_SIZES)
 @pytest.mark.parametrize("hole", [False, True])
 def test_precond_mixed(ctx, oracle, pc, mode, rel, M, N, hole):

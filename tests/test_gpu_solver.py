@@ -78,6 +78,9 @@ def oracle_sensitivity(oracle, psi, mask, valid=None, samples=3, **kw):
 
 
 FIXED_CASES = [("peaks64", None), ("ragged", None), ("hole", "hole")]
+# the paper's five, the DCT Poisson preconditioner and the two-colour ordered
+# ILU(0), IC(0) and SSOR
+ALL_PCS = ["none", "jacobi", "ilu0", "ic0", "ssor", "dct", "ilu0_rb", "ic0_rb", "ssor_rb"]
 
 
 def _case(name):
@@ -91,7 +94,7 @@ def _case(name):
     return psi, synth.hole_mask(96, 80, 0.10, seed=10)
 
 
-@pytest.mark.parametrize("pc", ["none", "jacobi", "ilu0", "ic0", "ssor", "dct"])
+@pytest.mark.parametrize("pc", ALL_PCS)
 @pytest.mark.parametrize("case", ["peaks64", "ragged", "hole"])
 @pytest.mark.parametrize("k_max", [1, 3])
 def test_fp64_fixed_work_matches_oracle(ctx, oracle, pc, case, k_max):
@@ -117,7 +120,7 @@ def test_fp64_fixed_work_matches_oracle(ctx, oracle, pc, case, k_max):
         assert np.array_equal(phi[~valid], phi0[~valid])
 
 
-@pytest.mark.parametrize("pc", ["none", "jacobi", "ilu0", "ic0", "ssor", "dct"])
+@pytest.mark.parametrize("pc", ALL_PCS)
 def test_fp64_peaks64_matches_oracle(ctx, oracle, pc):
     """64x64 peaks map, p = 0, tau = 0.01, 10 outer iterations, inner relres
     1e-6 (the small plain-FP64 workload).  Bounded by the oracle's own
@@ -137,7 +140,7 @@ def test_fp64_peaks64_matches_oracle(ctx, oracle, pc):
 
 
 @pytest.mark.parametrize("M,N", [(37, 53), (1, 60), (60, 1), (130, 77)])
-@pytest.mark.parametrize("pc", ["jacobi", "ilu0", "dct"])
+@pytest.mark.parametrize("pc", ["jacobi", "ilu0", "dct", "ilu0_rb", "ssor_rb"])
 def test_fp64_ragged_matches_oracle(ctx, oracle, M, N, pc):
     psi, _ = synth.peaks_map(M, N, scale=2.0, sigma=0.2, seed=M + N)
     ref, sens = oracle_sensitivity(oracle, psi, None, p=1.0, precond=pc, k_max=4, outer_tol=0.0)
@@ -166,7 +169,7 @@ def test_fp64_paper_stop_rule_and_random_start(ctx, oracle):
     assert d <= max(1e-6, 50 * sens)
 
 
-@pytest.mark.parametrize("pc", ["none", "jacobi", "ilu0", "ic0", "ssor", "dct"])
+@pytest.mark.parametrize("pc", ALL_PCS)
 @pytest.mark.parametrize("M,N", [(40, 32), (72, 56)])
 def test_paper_faithful_mode(ctx, oracle, pc, M, N):
     """The paper's experiment settings (Section 3): random start, inner test
@@ -283,7 +286,7 @@ def test_one_pixel_map(ctx):
 
 
 @pytest.mark.parametrize("shape", [(1, 200), (200, 1)])
-@pytest.mark.parametrize("pc", ["none", "jacobi", "ilu0", "ic0", "ssor", "dct"])
+@pytest.mark.parametrize("pc", ALL_PCS)
 def test_one_dimensional_maps(ctx, oracle, shape, pc):
     rng = np.random.default_rng(4)
     phi_true = np.cumsum(rng.normal(0, 0.6, shape[0] * shape[1])).reshape(shape)
