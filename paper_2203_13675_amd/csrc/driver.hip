@@ -547,7 +547,7 @@ struct Pcg {
       }
       if ((rc = read_states(ctx))) return rc;
       std::vector<int> still;
-      long long nextK = Kcap;
+      std::vector<long long> guesses;
       for (int m : set) {
         const MapState& s = e.hms[m];
         if (s.state == kDone || s.state == kCap || s.state == kBreakdown || s.state == kStall)
@@ -563,12 +563,30 @@ struct Pcg {
         }
         prev_metric[m] = metric;
         prev_l[m] = s.l;
-        nextK = std::min(nextK, guess);
+        guesses.push_back(guess);
       }
       if (still.empty()) break;
       if (still.size() != set.size()) {
-        set = still;
-        if ((rc = engine_activate(ctx, set, &nt, &nd))) return rc;
+        // Finished maps' tiles skip all work, so the lists are rebuilt (a
+        // host round trip of several uploads) only once they hold at least
+        // 10 % dead stencil tiles.
+        long long live = 0;
+        for (int m : still) live += e.hdesc[m].ntiles;
+        if (live * 10 <= (long long)nt * 9) {
+          set = still;
+          if ((rc = engine_activate(ctx, set, &nt, &nd))) return rc;
+        }
+      }
+      // Round length: the median of the maps' predicted remaining iterations.
+      // A map that meets its bound inside a round stops iterating and waits
+      // for the round's confirmation, so a longer round wastes no work on it,
+      // while every round costs a confirmation pass and a host round trip
+      // (the earliest map's prediction made rounds 3x more frequent and the
+      // batch 3 % slower).
+      long long nextK = Kcap;
+      if (!guesses.empty()) {
+        std::nth_element(guesses.begin(), guesses.begin() + guesses.size() / 2, guesses.end());
+        nextK = guesses[guesses.size() / 2];
       }
       K = std::max(2LL, std::min(nextK, Kcap));
     }
