@@ -64,6 +64,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--maps", type=int, default=256)
+    ap.add_argument("--workload", default="batch256",
+                    choices=["batch256", "peaks1024", "gauss2048_hole", "ramp4096"],
+                    help="batch256 (default, the benchmark line) or one of the single-map "
+                         "workloads, run through the same path for profiling")
     ap.add_argument("--outer", type=int, default=10)
     ap.add_argument("--dct-mode", default="fp16_scaled")
     ap.add_argument("--fp64-compare", type=int, default=1,
@@ -90,10 +94,22 @@ def main():
     from paper_2203_13675_amd import synth
     from paper_2203_13675_amd.binding import Context, default_options, KERNEL_CLASSES
 
-    shapes = synth.batch_sizes(a.maps, seed=3000)
-    maps = synth.batch_maps(a.maps, seed=3000)
-    total_px = sum(m * n for m, n in shapes)
     dev = torch.device("cuda:0")
+    masks = None
+    if a.workload == "batch256":
+        shapes = synth.batch_sizes(a.maps, seed=3000)
+        maps = synth.batch_maps(a.maps, seed=3000)
+        desc = ("batch of %d uneven random-Gaussian maps (sides in {128..1024}), p=0, tau=0.01, "
+                "%d outer iterations, DCT preconditioner, relres 1e-6" % (a.maps, a.outer))
+    else:
+        psi1, mask1, truth1 = synth.workload(a.workload)
+        shapes = [psi1.shape]
+        maps = [(psi1, truth1)]
+        if mask1 is not None:
+            masks = [torch.from_numpy(mask1).to(dev)]
+        desc = ("%s: one %dx%d map, p=0, tau=0.01, %d outer iterations, DCT preconditioner, "
+                "relres 1e-6" % ((a.workload,) + tuple(psi1.shape) + (a.outer,)))
+    total_px = sum(m * n for m, n in shapes)
     psis = [torch.from_numpy(p).to(dev) for p, _ in maps]
     phis = [torch.zeros_like(t) for t in psis]
     opts = dict(p=0.0, eps=0.01, preconditioner="dct", tol=1e-6)
@@ -101,11 +117,11 @@ def main():
     o = default_options(precision="mixed", dct_mode=a.dct_mode, k_max=a.outer, outer_tol=0.0)
 
     def step():
-        return ctx.batch(psis, phis=phis, options=o, **opts)
+        return ctx.batch(psis, masks, phis=phis, options=o, **opts)
 
     tune = None
     if a.autotune:
-        best, tune_ms = ctx.autotune(psis, phis=phis, options=o, probe_iters=20,
+        best, tune_ms = ctx.autotune(psis, masks, phis=phis, options=o, probe_iters=20,
                                      cache_path=a.tune_cache, **opts)
         tune = {"tuning": best, "autotune_ms": tune_ms}
     ctx.set_tuning(use_graph=a.graph)
@@ -154,7 +170,7 @@ def main():
         name, kt = dom
         launches = max(kt["launches"], 1)
         per_launch_s = kt["ms"] / 1e3 / launches
-        traffic = measured_traffic(name, a.dct_mode, a.maps)
+        traffic = measured_traffic(name, a.dct_mode, a.maps) if a.workload == "batch256" else None
         common = {"kernel": name, "traffic": traffic, "traffic_unit": "bytes per launch",
                   "alg_bytes_per_launch": kt["bytes"] / launches,
                   "alg_flops_per_launch": kt["flops"] / launches,
@@ -184,10 +200,8 @@ def main():
         "value": value, "unit": "Mpixel/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
         "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "batch of %d uneven random-Gaussian maps (sides in "
-                               "{128..1024}), p=0, tau=0.01, %d outer iterations, DCT "
-                               "preconditioner, relres 1e-6" % (a.maps, a.outer),
-                   "maps": a.maps, "total_pixels": total_px, "outer_iters": a.outer,
+        "config": {"workload": desc,
+                   "maps": len(shapes), "total_pixels": total_px, "outer_iters": a.outer,
                    "precision": "mixed: f32 CG vectors, %s DCT on MFMA, f64 dots and "
                                 "residual refinement" % a.dct_mode},
         "pcg_iters_per_step": inner, "cg_iters_per_s": inner / dt,
@@ -205,8 +219,9 @@ def main():
         t0 = time.perf_counter()
         o64 = default_options(precision="fp64", k_max=a.outer, outer_tol=0.0)
         it64 = 0
-        for ps, ph in zip(psis, phis):
-            it64 += ctx.solve(ps, phi=ph, options=o64, **opts).stats["inner_iters_total"]
+        for k, (ps, ph) in enumerate(zip(psis, phis)):
+            mk = masks[k] if masks is not None else None
+            it64 += ctx.solve(ps, mk, phi=ph, options=o64, **opts).stats["inner_iters_total"]
         torch.cuda.synchronize()
         t64 = time.perf_counter() - t0
         out["fp64_sequential"] = {"value": total_px / t64 / 1e6, "unit": "Mpixel/s",
@@ -223,7 +238,7 @@ def main():
         torch.cuda.synchronize()
         out["calib_copy_bytes_each"] = 2 * n * 4
 
-    if a.cpu_baseline and not a.profile:
+    if a.cpu_baseline and not a.profile and a.workload == "batch256":
         out["cpu_baseline"] = cpu_baseline(maps, shapes, a.outer)
     ctx.close()
     print(json.dumps(out))
