@@ -21,7 +21,8 @@
 namespace lpu {
 
 // engine_kernels.hip / engine_dct.hip
-void e_wrapdiff(hipStream_t st, const Engine& e, int ntiles);
+void e_wrapdiff(hipStream_t st, const Engine& e, int ntiles, bool zero_phi);
+void e_check(hipStream_t st, const Engine& e, int ntiles, unsigned int* bad);
 template <typename T> void e_weights(hipStream_t, const Engine&, int, double, double);
 template <typename T> void e_diag(hipStream_t, const Engine&, int, bool);
 template <typename T> void e_rhs(hipStream_t, const Engine&, int, int);
@@ -609,25 +610,21 @@ static int run_maps(lp_unwrap_ctx* ctx, int n, const lpu_map* maps, double p, do
   Engine& e = ctx->eng;
   KTimer& kt = ctx->kt;
 
-  // inputs must be finite (mask in [0, 1])
+  std::vector<int> all(n);
+  for (int m = 0; m < n; ++m) all[m] = m;
+  int nt = 0, nd = 0;
+  if ((rc = engine_activate(ctx, all, &nt, &nd))) return rc;
+
+  // inputs must be finite (mask in [0, 1]); one launch over every map's tiles
   LPU_HIP_CHECK(ctx, hipMemsetAsync(e.counts + 8, 0, 4, st));
-  for (int m = 0; m < n; ++m)
-    launch_finite_check(st, (size_t)maps[m].rows * maps[m].cols, maps[m].psi, maps[m].mask,
-                        (unsigned int*)(e.counts + 8));
+  e_check(st, e, nt, (unsigned int*)(e.counts + 8));
   unsigned int bad = 0;
   LPU_HIP_CHECK(ctx, hipMemcpyAsync(&bad, e.counts + 8, 4, hipMemcpyDeviceToHost, st));
   LPU_HIP_CHECK(ctx, hipStreamSynchronize(st));
   if (bad) return set_error(ctx, LPU_ERR_NONFINITE, "psi or mask holds NaN/Inf (or mask outside [0,1])");
 
-  for (int m = 0; m < n; ++m)
-    if (!o.use_phi0)
-      LPU_HIP_CHECK(ctx, hipMemsetAsync(maps[m].phi, 0, sizeof(double) * maps[m].rows * maps[m].cols, st));
-
-  std::vector<int> all(n);
-  for (int m = 0; m < n; ++m) all[m] = m;
-  int nt = 0, nd = 0;
-  if ((rc = engine_activate(ctx, all, &nt, &nd))) return rc;
-  e_wrapdiff(st, e, nt);
+  // wrapped differences; phi = 0 unless the caller supplies the start value
+  e_wrapdiff(st, e, nt, !o.use_phi0);
 
   const bool need_diag = pc == kPcJacobi;
   bool any_mask = false;
@@ -855,7 +852,7 @@ int step_wrapdiff(lp_unwrap_ctx* ctx, int M, int N, const double* psi, double* d
   int rc = step_setup(ctx, M, N, 8, false, psi, nullptr, nullptr);
   if (rc) return rc;
   Engine& e = ctx->eng;
-  e_wrapdiff(ctx->stream, e, e.total_tiles);
+  e_wrapdiff(ctx->stream, e, e.total_tiles, false);
   const size_t b = (size_t)M * N * 8;
   if ((rc = copy_in(ctx, dx, e.dx, b)) || (rc = copy_in(ctx, dy, e.dy, b))) return rc;
   LPU_HIP_CHECK(ctx, hipStreamSynchronize(ctx->stream));

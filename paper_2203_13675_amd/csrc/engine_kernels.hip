@@ -291,11 +291,14 @@ __device__ __forceinline__ double wrap_w(double x) {
   return x - kTwoPi * k;
 }
 
-__global__ void __launch_bounds__(64) k_e_wrapdiff(EArgs A) {
+// zero_phi: also set the caller's phi to 0 (the start value when the caller
+// does not supply one)
+__global__ void __launch_bounds__(64) k_e_wrapdiff(EArgs A, int zero_phi) {
   TILE_LOOP(A) {
     const int g = A.act[t_];
     const TilePos tp = tile_pos(A.desc, A.tile_map, g);
     const double* psi = A.desc[tp.m].psi;
+    double* phi = A.desc[tp.m].phi;
     double* dx = A.dx + tp.off;
     double* dy = A.dy + tp.off;
     march_points(tp, [&](int i, int j) {
@@ -303,8 +306,27 @@ __global__ void __launch_bounds__(64) k_e_wrapdiff(EArgs A) {
       const double c = psi[p];
       dx[p] = (j < tp.N - 1) ? wrap_w(psi[p + 1] - c) : 0.0;
       dy[p] = (i < tp.M - 1) ? wrap_w(psi[p + tp.N] - c) : 0.0;
+      if (zero_phi) phi[p] = 0.0;
     });
   }
+}
+
+// Input check of every map in one launch: *bad |= 1 when psi holds a
+// non-finite value or the mask one outside [0, 1].
+__global__ void __launch_bounds__(64) k_e_check(EArgs A, unsigned int* bad) {
+  unsigned int b = 0;
+  TILE_LOOP(A) {
+    const int g = A.act[t_];
+    const TilePos tp = tile_pos(A.desc, A.tile_map, g);
+    const double* psi = A.desc[tp.m].psi;
+    const float* mask = A.desc[tp.m].mask;
+    march_points(tp, [&](int i, int j) {
+      const size_t p = (size_t)i * tp.N + j;
+      if (!isfinite(psi[p])) b = 1;
+      if (mask && !(isfinite(mask[p]) && mask[p] >= 0.0f && mask[p] <= 1.0f)) b = 1;
+    });
+  }
+  if (b) atomicOr(bad, 1u);
 }
 
 __device__ __forceinline__ double abs_pow(double r, double e) {
@@ -874,8 +896,13 @@ EArgs make_args(const Engine& e) {
   return a;
 }
 
-void e_wrapdiff(hipStream_t st, const Engine& e, int ntiles) {
-  hipLaunchKernelGGL(k_e_wrapdiff, dim3(egrid(e, ntiles)), dim3(64), 0, st, make_args(e));
+void e_wrapdiff(hipStream_t st, const Engine& e, int ntiles, bool zero_phi) {
+  hipLaunchKernelGGL(k_e_wrapdiff, dim3(egrid(e, ntiles)), dim3(64), 0, st, make_args(e),
+                     zero_phi ? 1 : 0);
+}
+
+void e_check(hipStream_t st, const Engine& e, int ntiles, unsigned int* bad) {
+  hipLaunchKernelGGL(k_e_check, dim3(egrid(e, ntiles)), dim3(64), 0, st, make_args(e), bad);
 }
 
 template <typename T>

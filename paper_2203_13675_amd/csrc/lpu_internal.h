@@ -161,8 +161,6 @@ int step_precond(lp_unwrap_ctx* ctx, int M, int N, int pc, int dct_mode, double 
                  const T* V, const T* r, T* s);
 
 // small utilities (util.hip)
-void launch_finite_check(hipStream_t st, size_t n, const double* psi, const float* mask,
-                         unsigned int* bad);
 template <typename T>
 void launch_scale_by(hipStream_t st, size_t n, const T* a, const T* b, T* out);
 

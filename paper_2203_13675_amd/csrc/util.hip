@@ -1,25 +1,7 @@
-// Small elementwise utilities: input validation and a pointwise product.
+// Small elementwise utility: a pointwise product.
 #include "lpu_internal.h"
 
 namespace lpu {
-
-// *bad |= 1 when psi holds a non-finite value or the mask one outside [0, 1].
-__global__ void k_finite(size_t n, const double* __restrict__ psi, const float* __restrict__ mask,
-                         unsigned int* bad) {
-  unsigned int b = 0;
-  for (size_t p = blockIdx.x * (size_t)blockDim.x + threadIdx.x; p < n;
-       p += (size_t)gridDim.x * blockDim.x) {
-    if (!isfinite(psi[p])) b = 1;
-    if (mask && !(isfinite(mask[p]) && mask[p] >= 0.0f && mask[p] <= 1.0f)) b = 1;
-  }
-  if (b) atomicOr(bad, 1u);
-}
-
-void launch_finite_check(hipStream_t st, size_t n, const double* psi, const float* mask,
-                         unsigned int* bad) {
-  const int grid = (int)std::min<size_t>((n + 255) / 256, 1024);
-  hipLaunchKernelGGL(k_finite, dim3(std::max(grid, 1)), dim3(256), 0, st, n, psi, mask, bad);
-}
 
 template <typename T>
 __global__ void k_scale_by(size_t n, const T* __restrict__ a, const T* __restrict__ b,
