@@ -71,13 +71,13 @@ static double now_ms() {
 // engine set-up
 // ---------------------------------------------------------------------------
 static void engine_free(Engine& e) {
-  void* ptrs[] = {e.desc, e.ms, e.tile_map, e.dtile_map, e.act, e.dact, e.mact, e.fcnt, e.gcnt, e.eot, e.counts,
+  // counts, mact, act and dact live in one allocation that starts at counts
+  void* ptrs[] = {e.desc, e.ms, e.tile_map, e.dtile_map, e.fcnt, e.gcnt, e.eot, e.counts,
                   e.dx, e.dy, e.phi_prev, e.r64, e.U, e.V, e.aux, e.x[0], e.x[1], e.d[0],
                   e.d[1], e.r, e.s, e.q, e.b, e.t1, e.t2, e.iso, e.P};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (e.hms) (void)hipHostFree(e.hms);
-  if (e.hcounts) (void)hipHostFree(e.hcounts);
   if (e.hlist) (void)hipHostFree(e.hlist);
   e = Engine();
 }
@@ -197,14 +197,20 @@ static int engine_setup(lp_unwrap_ctx* ctx, int n, const lpu_map* maps, int elem
     A((void**)&e.tile_map, 4 * (size_t)tiles);
     A((void**)&e.dtile_map, 4 * (size_t)dtiles);
     A((void**)&e.eot, sizeof(EoTile) * 2 * (size_t)std::max(dtiles, 1));
-    A((void**)&e.act, 4 * (size_t)tiles);
+    // the lists of one activation, in one allocation laid out like the
+    // pinned staging (counts, active maps, stencil tiles, the two DCT
+    // lists), so the first three go up in one copy
     const long long dcap = (long long)dtiles + 8LL * (n + 1) * 256 + 64;
-    A((void**)&e.dact, 4 * (size_t)(2 * dcap));
-    A((void**)&e.mact, 4 * (size_t)n);
+    const size_t list_ints = kListHead + (size_t)n + (size_t)tiles + 2 * (size_t)dcap;
+    A((void**)&e.counts, 4 * list_ints);
+    if (ok) {
+      e.mact = e.counts + kListHead;
+      e.act = e.mact + n;
+      e.dact = e.act + tiles;
+    }
     A((void**)&e.fcnt, 4 * (size_t)n);
     // groups <= tiles / G + dtiles / G + 2 n for any layout within these capacities
     A((void**)&e.gcnt, 4 * ((size_t)(tiles + dtiles) / kArriveGroup + 2 * (size_t)n + 8));
-    A((void**)&e.counts, 64);
     A((void**)&e.dx, 8 * (size_t)cpx);
     A((void**)&e.dy, 8 * (size_t)cpx);
     A((void**)&e.phi_prev, 8 * (size_t)cpx);
@@ -215,9 +221,7 @@ static int engine_setup(lp_unwrap_ctx* ctx, int n, const lpu_map* maps, int elem
     A((void**)&e.iso, (size_t)cpx);
     A((void**)&e.P, 8 * (size_t)kNumSlots * pst);
     if (ok && hipHostMalloc((void**)&e.hms, sizeof(MapState) * n) != hipSuccess) ok = false;
-    if (ok && hipHostMalloc((void**)&e.hcounts, 64) != hipSuccess) ok = false;
-    if (ok && hipHostMalloc((void**)&e.hlist, 4 * ((size_t)tiles + 2 * dcap + n + 16)) != hipSuccess)
-      ok = false;
+    if (ok && hipHostMalloc((void**)&e.hlist, 4 * list_ints) != hipSuccess) ok = false;
     e.dlist_cap = dcap;
     if (!ok) {
       engine_free(e);
@@ -316,7 +320,11 @@ static int engine_activate(lp_unwrap_ctx* ctx, const std::vector<int>& set, int*
     LPU_HIP_CHECK(ctx, hipEventSynchronize(ctx->list_event));
     ctx->list_event_live = false;
   }
-  int* h = e.hlist;
+  // staging with the device layout: counts, maps, stencil tiles, DCT lists
+  int* hc = e.hlist;
+  int* hm = hc + kListHead;
+  int* h = hm + e.cap_maps;
+  int* hd = h + e.cap_tiles;
   int nt = 0;
   for (int m : set)
     for (int t = 0; t < e.hdesc[m].ntiles; ++t) h[nt++] = e.hdesc[m].tile0 + t;
@@ -327,7 +335,6 @@ static int engine_activate(lp_unwrap_ctx* ctx, const std::vector<int>& set, int*
   // XCD, consecutively, so the block's rows of X are re-read from that XCD's
   // L2; row blocks are balanced over the XCDs largest first.  Unused slots
   // hold -1.
-  int* hd = h + nt;
   int ndl[2] = {0, 0};
   for (int par = 0; par < 2; ++par) {
     int* out = hd + par * e.dlist_cap;
@@ -362,21 +369,20 @@ static int engine_activate(lp_unwrap_ctx* ctx, const std::vector<int>& set, int*
     ndl[par] = len;
   }
   const int nd = std::max(ndl[0], ndl[1]);
-  int* hm = hd + 2 * e.dlist_cap;
   int nm = 0;
   for (int m : set) hm[nm++] = m;
-  int* hc = hm + nm;
+  std::fill(hc, hc + kListHead, 0);
   hc[0] = nt;
   hc[1] = ndl[0];
   hc[2] = nm;
   hc[3] = ndl[1];
-  if (nt) LPU_HIP_CHECK(ctx, hipMemcpyAsync(e.act, h, 4 * (size_t)nt, hipMemcpyHostToDevice, st));
+  // counts, maps and stencil tiles in one copy, then each DCT list
+  const size_t head = (size_t)kListHead + (size_t)e.cap_maps + (size_t)nt;
+  LPU_HIP_CHECK(ctx, hipMemcpyAsync(e.counts, hc, 4 * head, hipMemcpyHostToDevice, st));
   for (int par = 0; par < 2; ++par)
     if (ndl[par])
       LPU_HIP_CHECK(ctx, hipMemcpyAsync(e.dact + par * e.dlist_cap, hd + par * e.dlist_cap,
                                         4 * (size_t)ndl[par], hipMemcpyHostToDevice, st));
-  if (nm) LPU_HIP_CHECK(ctx, hipMemcpyAsync(e.mact, hm, 4 * (size_t)nm, hipMemcpyHostToDevice, st));
-  LPU_HIP_CHECK(ctx, hipMemcpyAsync(e.counts, hc, 16, hipMemcpyHostToDevice, st));
   LPU_HIP_CHECK(ctx, hipEventRecord(ctx->list_event, st));
   ctx->list_event_live = true;
   *ntiles = nt;
@@ -462,9 +468,11 @@ struct Pcg {
     if (!pointwise()) tail(st, nt, nd, nm, kRun, kFinishIter);
   }
 
-  // Issue K iterations: as K launches of a captured graph of the body (one
-  // graph per launch shape, cached for this engine layout), or launch by
-  // launch while kernel timing is on.
+  // Issue K iterations: as launches of captured graphs of 8, 4, 2 and 1
+  // iterations of the body (one graph per chunk and launch shape, cached for
+  // this engine layout; consecutive kernels of one graph start back to back,
+  // while each graph launch costs a few microseconds), or launch by launch
+  // while kernel timing is on.
   int iterate(int nt, int nd, int nm, long long K) {
     hipStream_t st = ctx->stream;
     if (!ctx->tune.use_graph || ctx->kt.mask != 0) {
@@ -472,31 +480,37 @@ struct Pcg {
       return LPU_OK;
     }
     const Engine& e = ctx->eng;
-    const int key[6] = {egrid(e, nt), pointwise() ? 0 : dct_grid_for(e, nd), nm, pc, dct_kind,
-                        (int)sizeof(T)};
-    hipGraphExec_t ex = nullptr;
-    for (const GraphEntry& g : ctx->graphs)
-      if (std::equal(key, key + 6, g.key)) ex = g.exec;
-    if (!ex) {
-      hipStream_t cs = ctx->cap_stream;
-      LPU_HIP_CHECK(ctx, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-      body(cs, nt, nd, nm);
-      hipGraph_t g = nullptr;
-      LPU_HIP_CHECK(ctx, hipStreamEndCapture(cs, &g));
-      const hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(g);
-      if (ie != hipSuccess)
-        return set_error(ctx, LPU_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
-      if (ctx->graphs.size() >= 16) {
-        (void)hipGraphExecDestroy(ctx->graphs.front().exec);
-        ctx->graphs.erase(ctx->graphs.begin());
+    // the natural-order sweeps launch one block per map; every other kernel's
+    // shape depends on the tile counts only
+    const bool sweep = !pointwise() && !two_colour(pc) && pc != kPcDct;
+    for (int chunk = 8; chunk >= 1; chunk >>= 1) {
+      if (K < chunk) continue;
+      const int key[7] = {egrid(e, nt), pointwise() ? 0 : dct_grid_for(e, nd), sweep ? nm : 0, pc,
+                          dct_kind, (int)sizeof(T), chunk};
+      hipGraphExec_t ex = nullptr;
+      for (const GraphEntry& g : ctx->graphs)
+        if (std::equal(key, key + 7, g.key)) ex = g.exec;
+      if (!ex) {
+        hipStream_t cs = ctx->cap_stream;
+        LPU_HIP_CHECK(ctx, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        for (int k = 0; k < chunk; ++k) body(cs, nt, nd, nm);
+        hipGraph_t g = nullptr;
+        LPU_HIP_CHECK(ctx, hipStreamEndCapture(cs, &g));
+        const hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ie != hipSuccess)
+          return set_error(ctx, LPU_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+        if (ctx->graphs.size() >= 32) {
+          (void)hipGraphExecDestroy(ctx->graphs.front().exec);
+          ctx->graphs.erase(ctx->graphs.begin());
+        }
+        GraphEntry ge;
+        std::copy(key, key + 7, ge.key);
+        ge.exec = ex;
+        ctx->graphs.push_back(ge);
       }
-      GraphEntry ge;
-      std::copy(key, key + 6, ge.key);
-      ge.exec = ex;
-      ctx->graphs.push_back(ge);
+      for (; K >= chunk; K -= chunk) LPU_HIP_CHECK(ctx, hipGraphLaunch(ex, st));
     }
-    for (long long k = 0; k < K; ++k) LPU_HIP_CHECK(ctx, hipGraphLaunch(ex, st));
     return LPU_OK;
   }
 

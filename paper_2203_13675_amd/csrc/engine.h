@@ -26,6 +26,7 @@ constexpr int kEngineGrid = 4096;  // default cap on the blocks of the grid-stri
 constexpr int kDctGrid = 2048;     // default cap on the blocks of a DCT stage
 constexpr int kArriveGroup = 32;   // tiles per first-level arrival counter of the fused finishers
 constexpr int kNumSlots = 4;       // partial-sum slots
+constexpr int kListHead = 16;      // ints of counts[] ahead of the active-map list
 
 // DCT tables of one size n as seen by the kernels.
 struct DctTabDev {
@@ -119,9 +120,9 @@ struct Engine {
   int* gcnt = nullptr;       // per-group arrival counters (groups of kArriveGroup tiles of one map)
   EoTile* eot = nullptr;     // even/odd DCT tile records, [parity][global DCT tile]
   int* counts = nullptr;     // [0] active tiles, [1] DCT list (even stages), [2] active
-                             // maps, [3] DCT list (odd stages)
-  int* hcounts = nullptr;    // pinned
-  int* hlist = nullptr;      // pinned staging for the lists
+                             // maps, [3] DCT list (odd stages); kListHead ints, followed
+                             // in the same allocation by mact, act and dact
+  int* hlist = nullptr;      // pinned staging for counts and the lists, same layout
   // FP64 arrays
   double* dx = nullptr;
   double* dy = nullptr;

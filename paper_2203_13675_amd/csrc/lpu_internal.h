@@ -104,7 +104,7 @@ namespace lpu {
 // Executable graph of one PCG iteration for one launch shape; valid until the
 // engine is laid out again (the cache is emptied by every engine set-up).
 struct GraphEntry {
-  int key[6];
+  int key[7];  // launch shape, preconditioner, precision, iterations per graph
   hipGraphExec_t exec;
 };
 
