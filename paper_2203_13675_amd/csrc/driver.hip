@@ -12,6 +12,7 @@
 // the predicted iterations left.
 
 #include <algorithm>
+#include <map>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -660,6 +661,11 @@ static int run_maps(lp_unwrap_ctx* ctx, int n, const lpu_map* maps, double p, do
 
   auto credit = [&](const std::vector<int>& set) {
     // algorithmic figures of the PCG launches that did work
+    // the DCT tables of one side length serve every map of that side in a
+    // launch, so they count once per launch in which any such map is active:
+    // a map is active in a prefix of the run's applications, so that is the
+    // largest application count among the maps of that side
+    std::map<int, long long> side_apps;
     for (int m : set) {
       const MapState& s = e.hms[m];
       const double px = (double)maps[m].rows * maps[m].cols, el = (double)sizeof(T);
@@ -673,14 +679,16 @@ static int run_maps(lp_unwrap_ctx* ctx, int n, const lpu_map* maps, double p, do
         const int kd = pcg.dct_kind;
         const double prod = (kd == 2 || kd == 4) ? 3.0 : 1.0;
         const double half = kd >= 4 ? 0.5 : 1.0;
-        const double tab = kd == 0 ? 8.0 : (kd == 1 ? 4.0 : ((kd == 2 || kd == 4) ? 4.0 : 2.0));
         // X in, Out out per stage (the scaled-fp16 even/odd path keeps the
-        // three intermediates in 2 bytes), the tables, r in the last stage
-        const double io = kd == 5 ? px * (4.0 + 2.0 + 2.0 + 2.0 + 2.0 + 2.0 + 2.0 + 4.0)
-                                  : 8.0 * px * el;
-        const double bytes = io + 2.0 * half * Nn * Nn * tab + 2.0 * half * Mm * Mm * tab + px * el;
-        kt.credit(LPU_KC_DCT, 4 * s.nfinish, s.nfinish * bytes,
+        // three intermediates in 2 bytes), and r again in the last stage
+        const double io = (kd == 5 ? px * (4.0 + 2.0 + 2.0 + 2.0 + 2.0 + 2.0 + 2.0 + 4.0)
+                                   : 8.0 * px * el) + px * el;
+        kt.credit(LPU_KC_DCT, 4 * s.nfinish, s.nfinish * io,
                   s.nfinish * 4.0 * px * (Mm + Nn) * prod * half);
+        for (int side : {maps[m].rows, maps[m].cols}) {
+          long long& a = side_apps[side];
+          a = std::max(a, s.nfinish);
+        }
       } else if (two_colour(pc)) {
         // per application, two passes: read r, pivots, U, V (+ s on half the
         // pixels in the second) and write s on half the pixels each
@@ -688,6 +696,16 @@ static int run_maps(lp_unwrap_ctx* ctx, int n, const lpu_map* maps, double p, do
       } else if (!pcg.pointwise()) {
         kt.credit(LPU_KC_SWEEP, s.nfinish, s.nfinish * px * el * 10.0, s.nfinish * px * 14.0);
       }
+    }
+    if (pc == kPcDct) {
+      // per application and side n: a forward and an inverse table of n x n
+      // entries (n x n/2 for the even/odd split), 2, 4 (the bf16 hi and lo
+      // planes, or FP32) or 8 bytes each
+      const int kd = pcg.dct_kind;
+      const double half = kd >= 4 ? 0.5 : 1.0;
+      const double tab = kd == 0 ? 8.0 : (kd == 1 ? 4.0 : ((kd == 2 || kd == 4) ? 4.0 : 2.0));
+      for (const auto& sa : side_apps)
+        kt.credit(LPU_KC_DCT, 0, (double)sa.second * 2.0 * half * sa.first * sa.first * tab, 0.0);
     }
   };
 
