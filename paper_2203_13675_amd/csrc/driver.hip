@@ -670,8 +670,17 @@ static int run_maps(lp_unwrap_ctx* ctx, int n, const lpu_map* maps, double p, do
       const MapState& s = e.hms[m];
       const double px = (double)maps[m].rows * maps[m].cols, el = (double)sizeof(T);
       const double jac = pc == kPcJacobi ? 1.0 : 0.0;
-      kt.credit(LPU_KC_SPMV, s.l, s.l * px * el * (6.0 + jac), s.l * px * 13.0);
-      kt.credit(LPU_KC_UPDATE, s.l, s.l * px * el * (6.0 + jac), s.l * px * 8.0);
+      // SpMV: read s (or r), d_old, U, V (+ inverse diagonal), write d, q,
+      // and x += alpha_p d_old (read and write x) after every update that was
+      // not a replacement; update: read r, q (+ inverse diagonal), write r,
+      // or at a replacement read x, d, U, V, b (+ inverse diagonal) and write
+      // x, r
+      const double l = (double)s.l;
+      const double rep = s.period > 0 ? std::min(l, std::floor((l - 1.0) / s.period) + 1.0) : 0.0;
+      kt.credit(LPU_KC_SPMV, s.l, px * el * (l * (6.0 + jac) + 2.0 * std::max(0.0, l - 1.0 - rep)),
+                l * px * 13.0 + std::max(0.0, l - 1.0 - rep) * px * 2.0);
+      kt.credit(LPU_KC_UPDATE, s.l, px * el * ((l - rep) * (3.0 + jac) + rep * (7.0 + jac)),
+                (l - rep) * px * 6.0 + rep * px * 15.0);
       const double Mm = maps[m].rows, Nn = maps[m].cols;
       if (pc == kPcDct) {
         // per application: 4 contractions; MFMA products per multiply-add

@@ -87,12 +87,14 @@ struct MapDesc {
 struct MapState {
   double delta_new, delta_old, delta0;
   double alpha, beta;
+  double alpha_p;              // x[xi] lacks alpha_p d[l & 1] (added by the next SpMV)
   double dq, rr, bb, rs;
   double thr_rr, thr_delta, tol2, eps2;
   double rr_chk;               // true residual at the last stagnation checkpoint
   long long l_chk, chk_gap;    // its iteration; least iterations between compared checkpoints
   long long l, l_max, period, nfinish;
   int state, rule, replaced, stall;  // stall: 1 = stop when the true residual stagnates
+  int xi, pad_;                // x[xi] holds the iterate (up to the pending term)
   float amax[4];
 };
 

@@ -33,6 +33,10 @@ template <typename T>
 struct R3 {
   T s, w, d;  // raw loads of one operand element (see the field loaders)
 };
+template <typename T>
+struct R4 {
+  T s, w, d, x;  // R3 and the iterate (SpMV)
+};
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 
@@ -148,10 +152,11 @@ __device__ __forceinline__ T stencil5(T uw, T uc, T vn, T vc, T xc, T xw, T xe, 
   return (uw + uc + vn + vc) * xc - uc * xe - uw * xw - vc * xs - vn * xn;
 }
 
-// March the tile: for every interior pixel call epi(i, j, x_ij, (A x)_ij).
-// The operand x is formed as make(load(i, j)): load issues the raw loads of
-// one element (zero outside the grid, through a clamped index), make combines
-// them.  Loads run two rows ahead of the arithmetic (operand row i + 2, U and
+// March the tile: for every interior pixel call epi(i, j, x_ij, (A x)_ij),
+// or epi(i, j, x_ij, (A x)_ij, raw_ij) when epi takes the element's raw loads
+// as well.  The operand x is formed as make(load(i, j)): load issues the raw
+// loads of one element (zero outside the grid, through a clamped index), make
+// combines them.  Loads run two rows ahead of the arithmetic (operand row i + 2, U and
 // V row i + 1 while row i is computed) and their values are first combined in
 // the next step, so a row's loads are in flight while the previous row is
 // computed and stored (vector loads and stores share one counter on this
@@ -174,13 +179,20 @@ __device__ __forceinline__ void march_stencil(const TilePos& tp, const T* __rest
     r.h = load(i, hj);
     return r;
   };
+  constexpr bool kRaw = std::is_invocable_v<E, int, int, T, T, const Raw&>;
+  auto call = [&](int i, int j, T xv, T ax, const Raw& raw) {
+    if constexpr (kRaw) epi(i, j, xv, ax, raw);
+    else epi(i, j, xv, ax);
+  };
   R2<T> xm, xc;
+  Row rcur;  // raw loads of the row being computed (kept only when epi reads them)
   {
     const Row rm = lrow(i0 - 1), rc = lrow(i0);
     xm.a = make(rm.a);
     xm.b = make(rm.b);
     xc.a = make(rc.a);
     xc.b = make(rc.b);
+    rcur = rc;
   }
   T xh = make(lrow(i0).h);
   Row rp = lrow(i0 + 1);
@@ -202,12 +214,13 @@ __device__ __forceinline__ void march_stencil(const TilePos& tp, const T* __rest
     neighbours(xc, xh, xw, xe);
     neighbours(uc, uh, uw, ue);
     if (FULL || ca < N)
-      epi(i, ca, xc.a, stencil5<T>(uw.a, uc.a, vn.a, vc.a, xc.a, xw.a, xe.a, xm.a, xp.a));
+      call(i, ca, xc.a, stencil5<T>(uw.a, uc.a, vn.a, vc.a, xc.a, xw.a, xe.a, xm.a, xp.a), rcur.a);
     if (FULL || cb < N)
-      epi(i, cb, xc.b, stencil5<T>(uw.b, uc.b, vn.b, vc.b, xc.b, xw.b, xe.b, xm.b, xp.b));
+      call(i, cb, xc.b, stencil5<T>(uw.b, uc.b, vn.b, vc.b, xc.b, xw.b, xe.b, xm.b, xp.b), rcur.b);
     xm = xc;
     xc = xp;
     xh = xph;
+    if constexpr (kRaw) rcur = rp;
     rp = rpp;
     vn = vc;
     vc = vnx;
@@ -465,9 +478,14 @@ __global__ void __launch_bounds__(64) k_e_pass(EArgs A, int op) {
     const TilePos tp = tile_pos(A.desc, A.tile_map, g);
     double* phi = A.desc[tp.m].phi;
     double* pp = A.phi_prev + tp.off;
-    const long long l = A.ms[tp.m].l;
+    const MapState& ms = A.ms[tp.m];
+    const long long l = ms.l;
     T* x0 = vec<T>(A.x0, tp.off);
-    const T* xf = cvec<T>((l & 1) ? A.x1 : A.x0, tp.off);
+    // the final iterate: x[xi] plus the pending step alpha_p d[l & 1]
+    const T* xf = cvec<T>(ms.xi ? A.x1 : A.x0, tp.off);
+    const T* dp = cvec<T>((l & 1) ? A.d1 : A.d0, tp.off);
+    const T ap = (T)ms.alpha_p;
+    const bool pend = ms.alpha_p != 0.0;
     double s0 = 0.0, s1 = 0.0;
     march_points(tp, [&](int i, int j) {
       const size_t p = (size_t)i * tp.N + j;
@@ -475,13 +493,13 @@ __global__ void __launch_bounds__(64) k_e_pass(EArgs A, int op) {
         case 0: pp[p] = phi[p]; break;
         case 1: x0[p] = (T)phi[p]; break;
         case 2: x0[p] = T(0); break;
-        case 3: phi[p] += (double)xf[p]; break;
+        case 3: phi[p] += (double)(pend ? xf[p] + ap * dp[p] : xf[p]); break;
         case 4: {
           const double dd = phi[p] - pp[p];
           s0 += dd * dd;
           s1 += pp[p] * pp[p];
         } break;
-        case 5: phi[p] = (double)xf[p]; break;
+        case 5: phi[p] = (double)(pend ? xf[p] + ap * dp[p] : xf[p]); break;
       }
     });
     if (op == 4) {
@@ -512,13 +530,24 @@ __global__ void __launch_bounds__(64) k_e_resid(EArgs A) {
     const T* V = cvec<T>(A.V, tp.off);
     const T* aux = cvec<T>(A.aux, tp.off);
     const T* b = cvec<T>(A.b, tp.off);
-    const T* x = cvec<T>(CONF && (l & 1) ? A.x1 : A.x0, tp.off);
+    // the iterate: x0 (init), or x[xi] plus the pending step alpha_p d[l & 1]
+    const T* x = cvec<T>(CONF && st.xi ? A.x1 : A.x0, tp.off);
+    const T* dp = cvec<T>((l & 1) ? A.d1 : A.d0, tp.off);
+    const T ap = CONF ? (T)st.alpha_p : T(0);
+    const bool pend = CONF && st.alpha_p != 0.0;
     T* r = vec<T>(A.r, tp.off);
     T* d0 = vec<T>(A.d0, tp.off);
     const int M = tp.M, N = tp.N;
     double srr = 0.0, srs = 0.0, sbb = 0.0;
-    march_tile<0, T>(tp, U, V, [&](int i, int j) { return ldz(x, i, j, M, N); },
-                     [](T v) { return v; },
+    march_tile<0, T>(tp, U, V,
+                     [&](int i, int j) {
+                       R3<T> v;  // x, unused, d (zero when no step is pending)
+                       v.s = ldz(x, i, j, M, N);
+                       v.w = T(1);
+                       v.d = pend ? ldz(dp, i, j, M, N) : T(0);
+                       return v;
+                     },
+                     [&](const R3<T>& v) { return pend ? v.s + ap * v.d : v.s; },
                      [&](int i, int j, T, T ax) {
                        const size_t p = (size_t)i * N + j;
                        const T bv = b[p];
@@ -541,7 +570,11 @@ __global__ void __launch_bounds__(64) k_e_resid(EArgs A) {
   }
 }
 
-// spmv: d_new = s + beta d_old; q = A d_new; partial d^T q
+// spmv: d_new = s + beta d_old; q = A d_new; partial d^T q.  Also adds the
+// previous iteration's step to the iterate, x += alpha_p d_old (the update
+// leaves it here: x is first needed again by a replacement or at the end, and
+// this kernel reads d_old anyway, so the step costs one read and one write of
+// x instead of two reads, a write and a second read of d in the update).
 template <typename T, int PC, int TH>
 __global__ void __launch_bounds__(64) k_e_spmv(EArgs A) {
   __shared__ double fred[3];
@@ -553,6 +586,9 @@ __global__ void __launch_bounds__(64) k_e_spmv(EArgs A) {
     if (st.state != kRun) continue;
     const long long l = st.l;
     const T beta = (T)st.beta;
+    const T ap = (T)st.alpha_p;
+    const bool pend = st.alpha_p != 0.0;
+    T* x = vec<T>(st.xi ? A.x1 : A.x0, tp.off);
     const T* U = cvec<T>(A.U, tp.off);
     const T* V = cvec<T>(A.V, tp.off);
     const T* aux = cvec<T>(A.aux, tp.off);
@@ -562,6 +598,9 @@ __global__ void __launch_bounds__(64) k_e_spmv(EArgs A) {
     T* q = vec<T>(A.q, tp.off);
     const int M = tp.M, N = tp.N;
     double sdq = 0.0;
+    // rows of the tile: x is loaded (with the operand's loads, two rows ahead)
+    // only for the tile's own elements, never for its halo
+    const int i_end = tp.i0 + (TH > 0 ? TH : tp.rows);
     march_tile<TH, T>(
         tp, U, V,
         [&](int i, int j) {
@@ -569,17 +608,20 @@ __global__ void __launch_bounds__(64) k_e_spmv(EArgs A) {
           const size_t p = clamp_at(i, j, M, N, ok);
           // unconditional loads through the clamped index, zeroed outside the grid
           const T s0 = src[p], d0 = dold[p];
-          R3<T> v;  // s (or r), inverse diagonal, d_old
+          R4<T> v;  // s (or r), inverse diagonal, d_old, x
           v.s = ok ? s0 : T(0);
           v.w = PC == kPcJacobi ? aux[p] : T(1);
           v.d = ok ? d0 : T(0);
+          v.x = T(0);
+          if (pend && i >= tp.i0 && i < i_end && j >= tp.j0 && j < tp.j0 + kTW) v.x = x[p];
           return v;
         },
-        [&](const R3<T>& v) { return (PC == kPcJacobi ? v.s * v.w : v.s) + beta * v.d; },
-        [&](int i, int j, T dv, T qv) {
+        [&](const R4<T>& v) { return (PC == kPcJacobi ? v.s * v.w : v.s) + beta * v.d; },
+        [&](int i, int j, T dv, T qv, const R4<T>& raw) {
           const size_t p = (size_t)i * N + j;
           dnew[p] = dv;
           q[p] = qv;
+          if (pend) x[p] = raw.x + ap * raw.d;
           sdq += (double)dv * (double)qv;
         });
     sdq = wave_sum(sdq);
@@ -593,8 +635,9 @@ __global__ void __launch_bounds__(64) k_e_spmv(EArgs A) {
   }
 }
 
-// update: x_new = x_old + alpha d; r -= alpha q, or r = b - A x_new when
-// l is a multiple of the replacement period; pointwise s; partials r.r, r.s
+// update: r -= alpha q (the step alpha d is added to x by the next SpMV), or,
+// when l is a multiple of the replacement period, x_new = x + alpha d into
+// the other x buffer and r = b - A x_new; pointwise s; partials r.r, r.s
 template <typename T, int PC, int TH>
 __global__ void __launch_bounds__(64) k_e_update(EArgs A) {
   __shared__ double fred[3];
@@ -611,14 +654,14 @@ __global__ void __launch_bounds__(64) k_e_update(EArgs A) {
     const T* V = cvec<T>(A.V, tp.off);
     const T* aux = cvec<T>(A.aux, tp.off);
     const T* b = cvec<T>(A.b, tp.off);
-    const T* xold = cvec<T>((l & 1) ? A.x1 : A.x0, tp.off);
-    T* xnew = vec<T>((l & 1) ? A.x0 : A.x1, tp.off);
-    const T* d = cvec<T>((l & 1) ? A.d0 : A.d1, tp.off);
     const T* q = cvec<T>(A.q, tp.off);
     T* r = vec<T>(A.r, tp.off);
     const int M = tp.M, N = tp.N;
     double srr = 0.0, srs = 0.0;
     if (replace) {
+      const T* xold = cvec<T>(st.xi ? A.x1 : A.x0, tp.off);
+      T* xnew = vec<T>(st.xi ? A.x0 : A.x1, tp.off);
+      const T* d = cvec<T>((l & 1) ? A.d0 : A.d1, tp.off);
       march_tile<TH, T>(
           tp, U, V,
           [&](int i, int j) {
@@ -648,19 +691,17 @@ __global__ void __launch_bounds__(64) k_e_update(EArgs A) {
       const int ja = min(tp.j0 + l, N - 1), jb = min(tp.j0 + 64 + l, N - 1);
       const bool oka = tp.j0 + l < N, okb = tp.j0 + 64 + l < N;
       const int kend = min(TH > 0 ? TH : tp.rows, M - tp.i0);
-      // four rows at a time: all loads of the group (through a clamped row)
+      // eight rows at a time: all loads of the group (through a clamped row)
       // are issued before its first store, so 32 loads per wave are in flight
       auto walk = [&](auto full_tag) {
         constexpr bool FULL = decltype(full_tag)::value;
-        constexpr int G = 4;
+        constexpr int G = 8;
         for (int k0 = 0; k0 < kend; k0 += G) {
-          T xv[G][2], dv[G][2], rv[G][2], qv[G][2], wv[G][2];
+          T rv[G][2], qv[G][2], wv[G][2];
 #pragma unroll
           for (int c = 0; c < G; ++c) {
             const size_t row = (size_t)min(tp.i0 + k0 + c, M - 1) * N;
             const size_t pa = row + ja, pb = row + jb;
-            xv[c][0] = xold[pa], xv[c][1] = xold[pb];
-            dv[c][0] = d[pa], dv[c][1] = d[pb];
             rv[c][0] = r[pa], rv[c][1] = r[pb];
             qv[c][0] = q[pa], qv[c][1] = q[pb];
             wv[c][0] = PC == kPcJacobi ? aux[pa] : T(1);
@@ -675,7 +716,6 @@ __global__ void __launch_bounds__(64) k_e_update(EArgs A) {
               if (!FULL && !(h ? okb : oka)) continue;
               const size_t p = row + (h ? jb : ja);
               const T rn = rv[c][h] - alpha * qv[c][h];
-              xnew[p] = xv[c][h] + alpha * dv[c][h];
               r[p] = rn;
               const T sv = PC == kPcJacobi ? rn * wv[c][h] : rn;
               srr += (double)rn * (double)rn;

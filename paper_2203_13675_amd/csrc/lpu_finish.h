@@ -151,11 +151,14 @@ __device__ inline void finish_map(const MapDesc* __restrict__ desc, MapState* ms
       s.thr_rr = s.tol2 * v[2];
       s.l = 0;
       s.replaced = 1;
+      s.alpha_p = 0.0;
+      s.xi = 0;
       if (v[2] == 0.0) s.state = kDone;
       else if (pointwise) map_finish(s, kFinishInit, v[1]);
       else s.state = kInitPc;
       break;
     case kFinAlpha:
+      s.alpha_p = 0.0;  // every tile of the SpMV has added the pending term
       s.dq = v[0];
       if (!(v[0] > 0.0) || !isfinite(v[0])) s.state = kBreakdown;
       else s.alpha = s.delta_new / v[0];
@@ -164,6 +167,10 @@ __device__ inline void finish_map(const MapDesc* __restrict__ desc, MapState* ms
       const bool replace = (s.l % s.period) == 0;
       s.rr = v[0];
       s.replaced = replace ? 1 : 0;
+      // a replacement wrote x + alpha d to the other buffer; otherwise the
+      // step alpha d is left to the next SpMV (x is not needed before it)
+      if (replace) s.xi ^= 1;
+      s.alpha_p = replace ? 0.0 : s.alpha;
       if (replace && stagnated(s, v[0])) {
         s.delta_old = s.delta_new;
         s.l += 1;  // the iterate of this update is the one returned
