@@ -31,14 +31,16 @@ PEAK_FP16_TFLOPS = 2500.0
 # measured HBM traffic per launch (rocprofv3 FETCH_SIZE / WRITE_SIZE passes,
 # scaled by a plain copy), valid while the kernel sources hash as recorded
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "traffic_batch256_fp16.txt")
-CLASS_SOURCE = {"dct": "engine_dct.hip", "spmv": "engine_kernels.hip",
-                "update": "engine_kernels.hip"}
+_SHARED_SOURCES = ["engine.h", "lpu_finish.h", "lpu_device.h", "lpu_internal.h"]
+CLASS_SOURCE = {"dct": ["engine_dct.hip"] + _SHARED_SOURCES,
+                "spmv": ["engine_kernels.hip"] + _SHARED_SOURCES,
+                "update": ["engine_kernels.hip"] + _SHARED_SOURCES}
 
 
 def measured_traffic(cls, dct_mode, maps):
     """Bytes per launch of kernel class `cls` from the committed counter summary,
     or None when the summary is missing, was taken on another workload, or the
-    kernel's source has changed since."""
+    kernel's source (its file or a header it includes) has changed since."""
     import hashlib
     if cls not in CLASS_SOURCE or maps != 256 or not os.path.exists(TRAFFIC_PROFILE):
         return None
@@ -49,10 +51,12 @@ def measured_traffic(cls, dct_mode, maps):
             fields[(parts[0], parts[1])] = parts[2]
         elif len(parts) == 2 and parts[0] == "dct_mode":
             fields["dct_mode"] = parts[1]
-    src = CLASS_SOURCE[cls]
-    path = os.path.join(ROOT, "paper_2203_13675_amd", "csrc", src)
-    digest = hashlib.sha256(open(path, "rb").read()).hexdigest()
-    if fields.get(("source_sha256", src)) != digest or fields.get("dct_mode") != dct_mode:
+    for src in CLASS_SOURCE[cls]:
+        path = os.path.join(ROOT, "paper_2203_13675_amd", "csrc", src)
+        digest = hashlib.sha256(open(path, "rb").read()).hexdigest()
+        if fields.get(("source_sha256", src)) != digest:
+            return None
+    if fields.get("dct_mode") != dct_mode:
         return None
     v = fields.get(("traffic_bytes_per_launch", cls))
     return float(v) if v is not None else None

@@ -428,6 +428,34 @@ __global__ void __launch_bounds__(256, 2) k_e_dct_eo(DArgs a) {
     fetch(0);
     __asm__ volatile("" ::: "memory");
     if (m_state != a.expect) continue;  // uniform over the block
+    const auto* lamMs = as_global(t_lam_m);
+    const auto* lamNs = as_global(t_lam_n);
+    // output index of column group j and first output row of row group i
+    auto out_c = [&](int j) {
+      const int c = c0 + 16 * j + lr;
+      return INV ? (hf ? n - 1 - c : c) : (hf ? h : 0) + c;
+    };
+    auto out_rb = [&](int i) { return r0 + wr + 16 * i + 4 * kq; };
+    // Everything the epilogue reads is loaded before its first store: loads
+    // and stores share one counter, so a load issued after a store would wait
+    // for that store too, one memory round trip per output tile.  The
+    // eigenvalues are requested here, ahead of the K loop; r and the
+    // isolated-pixel flags (stage 3) one column group ahead in the epilogue.
+    // Which stages an instance can run: the forward instances with fp16 input
+    // (or the split's, which serve both forward stages) run stage 1, the
+    // inverse instances with an FP32 output run stage 3.
+    constexpr bool kS1 = !INV && (SPLIT || IN16);
+    constexpr bool kS3 = INV && !OUT16;
+    const bool st1 = kS1 && a.stage == 1, st3 = kS3 && a.stage == 3;
+    float lam_c[4], lam_r[4][4];  // stage 1: eigenvalues along M and N (FP32)
+    if (st1) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) lam_c[j] = (float)lamMs[out_c(j)];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) lam_r[i][e] = (float)lamNs[out_rb(i) + e];
+    }
     if (!SPLIT) {
       // Scaled fp16: power-of-two scales from bounds that hold before any
       // value exists.  The transforms are orthonormal, so every stage output
@@ -484,31 +512,39 @@ __global__ void __launch_bounds__(256, 2) k_e_dct_eo(DArgs a) {
     // i.e. outputs (c, rb .. rb+3) with rb a multiple of 4
     const float* rv = reinterpret_cast<const float*>(a.rvec) + toff;
     const unsigned char* iso = (a.iso && t_iso) ? a.iso + toff : nullptr;
-    const auto* lamMs = as_global(t_lam_m);
-    const auto* lamNs = as_global(t_lam_n);
+    // stage 3: r and the isolated-pixel flags at the outputs of one column
+    // group, loaded one group ahead of the group being stored
+    f32x4 r_cur[4], r_nxt[4];
+    unsigned int z_cur[4], z_nxt[4];
+    auto load_rz = [&](int j, f32x4 (&rr)[4], unsigned int (&zz)[4]) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const size_t o = (size_t)out_c(j) * R + out_rb(i);
+        rr[i] = *as_global(reinterpret_cast<const f32x4*>(rv + o));
+        zz[i] = iso ? *as_global(reinterpret_cast<const unsigned int*>(iso + o)) : 0u;
+      }
+    };
+    if (st3) load_rz(0, r_cur, z_cur);
     double part = 0.0;
-    auto emit = [&](int c, int rb, const float (&y)[4]) {
+    auto emit = [&](int i, int j, const float (&y)[4]) {
+      const int c = out_c(j), rb = out_rb(i);
       float v[4] = {y[0], y[1], y[2], y[3]};
-      if (a.stage == 1) {
+      if (st1) {
         // spectrum ./ Lambda with the zero mode dropped; an FP32 reciprocal
         // (the preconditioner stays one fixed linear map)
-        const float lc = (float)lamMs[c];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const float l = lc + (float)lamNs[rb + e];
+          const float l = lam_c[j] + lam_r[i][e];
           v[e] = (c == 0 && rb + e == 0) ? 0.0f : v[e] * __builtin_amdgcn_rcpf(l);
         }
       }
-      if (a.stage == 3) {
+      if (st3) {
         // zero on isolated pixels; FP64 partial of r^T s (four outputs at once)
-        const size_t o = (size_t)c * R + rb;
-        const f32x4 r4 = *as_global(reinterpret_cast<const f32x4*>(rv + o));
-        const unsigned int z = iso ? *as_global(reinterpret_cast<const unsigned int*>(iso + o)) : 0u;
-        const float rr4[4] = {r4[0], r4[1], r4[2], r4[3]};
+        const unsigned int z = z_cur[i];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           if ((z >> (8 * e)) & 0xffu) v[e] = 0.0f;
-          part += (double)rr4[e] * (double)v[e];
+          part += (double)r_cur[i][e] * (double)v[e];
         }
       }
       if (OUT16) {
@@ -523,12 +559,11 @@ __global__ void __launch_bounds__(256, 2) k_e_dct_eo(DArgs a) {
     if (!INV) {
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int c = (hf ? h : 0) + c0 + 16 * j + lr;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const float y[4] = {acc[i][j][0] * inv_xs, acc[i][j][1] * inv_xs, acc[i][j][2] * inv_xs,
                               acc[i][j][3] * inv_xs};
-          emit(c, r0 + wr + 16 * i + 4 * kq, y);
+          emit(i, j, y);
         }
       }
     } else {
@@ -545,7 +580,7 @@ __global__ void __launch_bounds__(256, 2) k_e_dct_eo(DArgs a) {
       const int oh = hf ^ 1;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int c = c0 + 16 * j + lr;
+        if (st3 && j < 3) load_rz(j + 1, r_nxt, z_nxt);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const f32x4 o = xg[((oh * 2 + (w & 1)) * 16 + i * 4 + j) * 64 + lane];  // the other half
@@ -553,11 +588,15 @@ __global__ void __launch_bounds__(256, 2) k_e_dct_eo(DArgs a) {
                               (hf ? o[1] - acc[i][j][1] : acc[i][j][1] + o[1]) * inv_xs,
                               (hf ? o[2] - acc[i][j][2] : acc[i][j][2] + o[2]) * inv_xs,
                               (hf ? o[3] - acc[i][j][3] : acc[i][j][3] + o[3]) * inv_xs};
-          emit(hf ? n - 1 - c : c, r0 + wr + 16 * i + 4 * kq, y);
+          emit(i, j, y);
+        }
+        if (st3 && j < 3) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) r_cur[i] = r_nxt[i], z_cur[i] = z_nxt[i];
         }
       }
     }
-    if (a.stage == 3) {
+    if (st3) {
       double vv[1] = {part};
       block_sum<1>(vv, red);
       if (tid == 0) store_partial(a.P + 1 * a.pstride + g, vv[0]);
