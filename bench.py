@@ -15,6 +15,7 @@ comparison and the oracle's CPU rate on a bounded sample.
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import os
 import sys
@@ -133,13 +134,19 @@ def main():
     for _ in range(max(1, a.warmup)):
         step()
     torch.cuda.synchronize()
-    # timed region: the production path, no instrumentation
+    # timed region: the production path, no instrumentation.  Python's cyclic
+    # garbage collector is paused meanwhile (as timeit does): a full collection
+    # in a process holding torch takes tens of milliseconds and has nothing to
+    # do with the library's work
+    gc.collect()
+    gc.disable()
     t0 = time.perf_counter()
     stats = None
     for _ in range(a.steps):
         _, rc, stats = step()
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / a.steps
+    gc.enable()
     # kernel timing pass: one more step of the same workload with every kernel
     # class bracketed by HIP events on the library's stream (launch by launch:
     # events cannot be read per replay inside a captured graph)

@@ -145,7 +145,6 @@ static bool even_odd_ok(const lpu_map* maps, int n, bool mixed, int dct_mode) {
 static int engine_setup(lp_unwrap_ctx* ctx, int n, const lpu_map* maps, int elem, bool need_dct,
                         int dct_trows = kDT) {
   Engine& e = ctx->eng;
-  release_graphs(ctx);  // captured graphs hold the previous layout's launch shapes
   std::vector<MapDesc> hd(n);
   long long px = 0;
   int tiles = 0, dtiles = 0, maxN = 1, groups = 0;
@@ -185,6 +184,9 @@ static int engine_setup(lp_unwrap_ctx* ctx, int n, const lpu_map* maps, int elem
   const bool grow = px > e.cap_px || tiles > e.cap_tiles || dtiles > e.cap_dtiles ||
                     n > e.cap_maps || elem > e.elem;
   if (grow) {
+    // captured graphs hold the buffers' addresses; every other argument they
+    // capture is part of their key, and the layout itself is device data
+    release_graphs(ctx);
     engine_free(e);
     const long long cpx = std::max(px, 1LL);
     const size_t eb = (size_t)cpx * elem;
@@ -484,13 +486,17 @@ struct Pcg {
     // the natural-order sweeps launch one block per map; every other kernel's
     // shape depends on the tile counts only
     const bool sweep = !pointwise() && !two_colour(pc) && pc != kPcDct;
+    // every launch argument that is not a fixed buffer address
+    int om[2] = {0, 0};
+    if (!pointwise() && pc != kPcDct) std::memcpy(om, &omega, sizeof(om));
     for (int chunk = 8; chunk >= 1; chunk >>= 1) {
       if (K < chunk) continue;
-      const int key[7] = {egrid(e, nt), pointwise() ? 0 : dct_grid_for(e, nd), sweep ? nm : 0, pc,
-                          dct_kind, (int)sizeof(T), chunk};
+      const int key[kGraphKey] = {egrid(e, nt), pointwise() ? 0 : dct_grid_for(e, nd),
+                                  sweep ? nm : 0, sweep ? e.max_n : 0, pc, dct_kind,
+                                  (int)sizeof(T), e.th, om[0], om[1], chunk};
       hipGraphExec_t ex = nullptr;
       for (const GraphEntry& g : ctx->graphs)
-        if (std::equal(key, key + 7, g.key)) ex = g.exec;
+        if (std::equal(key, key + kGraphKey, g.key)) ex = g.exec;
       if (!ex) {
         hipStream_t cs = ctx->cap_stream;
         LPU_HIP_CHECK(ctx, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
@@ -501,12 +507,12 @@ struct Pcg {
         (void)hipGraphDestroy(g);
         if (ie != hipSuccess)
           return set_error(ctx, LPU_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
-        if (ctx->graphs.size() >= 32) {
+        if (ctx->graphs.size() >= 64) {
           (void)hipGraphExecDestroy(ctx->graphs.front().exec);
           ctx->graphs.erase(ctx->graphs.begin());
         }
         GraphEntry ge;
-        std::copy(key, key + 7, ge.key);
+        std::copy(key, key + kGraphKey, ge.key);
         ge.exec = ex;
         ctx->graphs.push_back(ge);
       }

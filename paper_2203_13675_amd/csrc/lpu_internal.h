@@ -103,8 +103,10 @@ namespace lpu {
 
 // Executable graph of one PCG iteration for one launch shape; valid until the
 // engine is laid out again (the cache is emptied by every engine set-up).
+constexpr int kGraphKey = 11;
 struct GraphEntry {
-  int key[7];  // launch shape, preconditioner, precision, iterations per graph
+  int key[kGraphKey];  // launch shapes, preconditioner and its parameters, precision,
+                       // tile height, iterations per graph
   hipGraphExec_t exec;
 };
 

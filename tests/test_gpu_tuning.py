@@ -99,6 +99,33 @@ def test_graph_replays_reuse_across_shrinking_sets(ctx):
         assert np.array_equal(first[k], eager[k])
 
 
+def test_graphs_kept_across_calls_follow_layout_and_parameters(ctx):
+    """Captured graphs outlive a call (they are dropped only when the work
+    buffers are reallocated): a later call with another map layout that fits
+    the same buffers, another tile height or another SSOR omega must replay
+    graphs that match it.  Every call is compared with a fresh context's
+    eager run of the same call, bit for bit."""
+    from paper_2203_13675_amd.binding import Context
+    big = synth.batch_maps(sides=[(256, 384), (384, 256), (128, 128)], seed=11)
+    small = synth.batch_maps(sides=[(128, 256), (256, 128)], seed=12)
+    calls = [(big, "dct", {}, 16), (small, "dct", {}, 16), (small, "dct", {}, 32),
+             (big, "ssor_rb", {"ssor_omega": 1.0}, 16), (big, "ssor_rb", {"ssor_omega": 1.6}, 16),
+             (small, "ssor", {"ssor_omega": 1.3}, 16), (small, "ssor", {"ssor_omega": 1.0}, 16)]
+    ctx.set_tuning(use_graph=1)
+    for maps, pc, kw, rows in calls:
+        ctx.set_tuning(tile_rows=rows)
+        got, sg = run_batch(ctx, maps, pc, **kw)
+        ref_ctx = Context(0)
+        try:
+            ref_ctx.set_tuning(use_graph=0, tile_rows=rows)
+            ref, sr = run_batch(ref_ctx, maps, pc, **kw)
+        finally:
+            ref_ctx.close()
+        for k in range(len(maps)):
+            assert np.array_equal(got[k], ref[k]), (pc, kw, rows, k)
+            assert sg[k]["inner_iters_total"] == sr[k]["inner_iters_total"]
+
+
 def test_set_tuning_rejects_bad_values(ctx):
     from paper_2203_13675_amd.binding import LpuError
     before = ctx.tuning()
