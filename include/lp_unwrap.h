@@ -265,7 +265,7 @@ typedef struct lpu_tuning {
     int max_batch_iters;  /* iterations issued between host reads of the map states: 2 .. 1024 */
 } lpu_tuning;
 
-/* Defaults: tile_rows 16, grid 4096, dct_grid 2048, use_graph 1,
+/* Defaults: tile_rows 16, grid 16384, dct_grid 2048, use_graph 1,
  * max_batch_iters 64. */
 void lpu_default_tuning(lpu_tuning* t);
 

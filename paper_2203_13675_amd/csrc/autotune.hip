@@ -129,7 +129,10 @@ extern "C" int lp_unwrap_autotune(lp_unwrap_ctx* ctx, int n_maps, const lpu_map*
       t.*field = v;
       const double tt = measure(t);
       if (err) return;
-      if (tt < cur_t) cur = t, cur_t = tt;
+      // a candidate must be 1 % faster to replace the current choice: the
+      // probe's run-to-run spread is about that, and the current tuning is
+      // the default or an earlier winner
+      if (tt < 0.99 * cur_t) cur = t, cur_t = tt;
     }
   };
   sweep(&lpu_tuning::tile_rows, {4, 8, 16, 32});

@@ -22,7 +22,7 @@ namespace lpu {
 constexpr int kTW = 128;  // stencil tile width (columns): two per lane of one wave
 constexpr int kTH = 16;   // default stencil tile height (rows), marched by the wave
 constexpr int kDT = 64;   // DCT output tile (64 x 64)
-constexpr int kEngineGrid = 4096;  // default cap on the blocks of the grid-stride tile kernels
+constexpr int kEngineGrid = 16384;  // default cap on the blocks of the grid-stride tile kernels
 constexpr int kDctGrid = 2048;     // default cap on the blocks of a DCT stage
 constexpr int kArriveGroup = 32;   // tiles per first-level arrival counter of the fused finishers
 constexpr int kNumSlots = 4;       // partial-sum slots

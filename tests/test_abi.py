@@ -82,5 +82,5 @@ def test_default_tuning(lib):
     from paper_2203_13675_amd import binding
     t = binding.LpuTuning()
     lib.lpu_default_tuning(ctypes.byref(t))
-    assert t.as_dict() == {"tile_rows": 16, "grid": 4096, "dct_grid": 2048, "use_graph": 1,
+    assert t.as_dict() == {"tile_rows": 16, "grid": 16384, "dct_grid": 2048, "use_graph": 1,
                            "max_batch_iters": 64}
