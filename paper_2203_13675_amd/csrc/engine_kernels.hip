@@ -264,6 +264,37 @@ __device__ __forceinline__ void march_points(const TilePos& tp, E epi) {
   }
 }
 
+// Elementwise walk in groups of G rows: load(i, j) issues every load of one
+// pixel (the walk passes in-grid coordinates, clamped for lanes and rows past
+// the map, whose results are dropped), store(i, j, v) computes and stores.
+// All loads of a group are issued before its first store: loads and stores
+// share one wait counter, so a load issued after a store would also wait for
+// the store, a memory round trip per pixel row.
+template <int G, typename L, typename S>
+__device__ __forceinline__ void march_points_grouped(const TilePos& tp, L load, S store) {
+  const int l = lane_id();
+  const int kend = min(tp.rows, tp.M - tp.i0);
+  const int ca = tp.j0 + l, cb = tp.j0 + 64 + l;
+  const int ja = min(ca, tp.N - 1), jb = min(cb, tp.N - 1);
+  using Val = decltype(load(0, 0));
+  for (int k0 = 0; k0 < kend; k0 += G) {
+    Val v[G][2];
+#pragma unroll
+    for (int c = 0; c < G; ++c) {
+      const int i = min(tp.i0 + k0 + c, tp.M - 1);
+      v[c][0] = load(i, ja);
+      v[c][1] = load(i, jb);
+    }
+#pragma unroll
+    for (int c = 0; c < G; ++c) {
+      if (k0 + c >= kend) break;  // uniform over the wave
+      const int i = tp.i0 + k0 + c;
+      if (ca < tp.N) store(i, ca, v[c][0]);
+      if (cb < tp.N) store(i, cb, v[c][1]);
+    }
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ T* vec(void* base, long long off) {
   return reinterpret_cast<T*>(base) + off;
@@ -363,23 +394,43 @@ __global__ void __launch_bounds__(64) k_e_weights(EArgs A, double e, double tau)
     const double* dy = A.dy + tp.off;
     T* U = vec<T>(A.U, tp.off);
     T* V = vec<T>(A.V, tp.off);
-    march_points(tp, [&](int i, int j) {
-      const size_t p = (size_t)i * tp.N + j;
-      const double c = phi[p];
-      double u = 0.0, v = 0.0;
-      if (j < tp.N - 1) {
-        const double r = phi[p + 1] - c - dx[p];
-        const double w = mask ? (double)fminf(mask[p], mask[p + 1]) : 1.0;
-        u = w * (tau / (abs_pow(r, e) + tau));
-      }
-      if (i < tp.M - 1) {
-        const double r = phi[p + tp.N] - c - dy[p];
-        const double w = mask ? (double)fminf(mask[p], mask[p + tp.N]) : 1.0;
-        v = w * (tau / (abs_pow(r, e) + tau));
-      }
-      U[p] = (T)u;
-      V[p] = (T)v;
-    });
+    struct Px {
+      double c, e, s, dx, dy;
+      float mc, me, ms;
+    };
+    march_points_grouped<2>(
+        tp,
+        [&](int i, int j) {
+          // neighbours outside the grid read the pixel itself (never used)
+          const size_t p = (size_t)i * tp.N + j;
+          const size_t pe = j < tp.N - 1 ? p + 1 : p, ps = i < tp.M - 1 ? p + tp.N : p;
+          Px x;
+          x.c = phi[p];
+          x.e = phi[pe];
+          x.s = phi[ps];
+          x.dx = dx[p];
+          x.dy = dy[p];
+          x.mc = mask ? mask[p] : 1.0f;
+          x.me = mask ? mask[pe] : 1.0f;
+          x.ms = mask ? mask[ps] : 1.0f;
+          return x;
+        },
+        [&](int i, int j, const Px& x) {
+          const size_t p = (size_t)i * tp.N + j;
+          double u = 0.0, v = 0.0;
+          if (j < tp.N - 1) {
+            const double r = x.e - x.c - x.dx;
+            const double w = mask ? (double)fminf(x.mc, x.me) : 1.0;
+            u = w * (tau / (abs_pow(r, e) + tau));
+          }
+          if (i < tp.M - 1) {
+            const double r = x.s - x.c - x.dy;
+            const double w = mask ? (double)fminf(x.mc, x.ms) : 1.0;
+            v = w * (tau / (abs_pow(r, e) + tau));
+          }
+          U[p] = (T)u;
+          V[p] = (T)v;
+        });
   }
 }
 
@@ -421,40 +472,66 @@ __global__ void __launch_bounds__(64) k_e_rhs(EArgs A, int mode) {
     T* bT = vec<T>(A.b, tp.off);
     double* r64 = A.r64 + tp.off;
     const int M = tp.M, N = tp.N;
+    const bool usephi = mode != 0;
     double srr = 0.0, sbb = 0.0;
-    march_points(tp, [&](int i, int j) {
-      const size_t p = (size_t)i * N + j;
-      const bool usephi = mode != 0;
-      const double pc = usephi ? phi[p] : 0.0;
-      double hx = 0.0, hy = 0.0, bx = 0.0, by = 0.0, hxw = 0.0, hyn = 0.0, bxw = 0.0, byn = 0.0;
-      if (j < N - 1) {
-        const double u = (double)U[p];
-        bx = u * dx[p];
-        hx = usephi ? u * (dx[p] - (phi[p + 1] - pc)) : bx;
-      }
-      if (i < M - 1) {
-        const double v = (double)V[p];
-        by = v * dy[p];
-        hy = usephi ? v * (dy[p] - (phi[p + N] - pc)) : by;
-      }
-      if (j > 0) {
-        const double u = (double)U[p - 1];
-        bxw = u * dx[p - 1];
-        hxw = usephi ? u * (dx[p - 1] - (pc - phi[p - 1])) : bxw;
-      }
-      if (i > 0) {
-        const double v = (double)V[p - N];
-        byn = v * dy[p - N];
-        hyn = usephi ? v * (dy[p - N] - (pc - phi[p - N])) : byn;
-      }
-      const double b = bxw + byn - bx - by;
-      const double r = hxw + hyn - hx - hy;
-      if (mode == 0) bT[p] = (T)b;
-      if (mode == 1) bT[p] = (T)r;
-      r64[p] = mode == 0 ? b : r;
-      srr += r * r;
-      sbb += b * b;
-    });
+    struct Px {
+      double pc, pe, pw, pn, ps, dxc, dxw, dyc, dyn;
+      T uc, uw, vc, vn;
+    };
+    march_points_grouped<2>(
+        tp,
+        [&](int i, int j) {
+          // neighbours outside the grid read the pixel itself (never used)
+          const size_t p = (size_t)i * N + j;
+          const size_t pe = j < N - 1 ? p + 1 : p, pw = j > 0 ? p - 1 : p;
+          const size_t pn = i > 0 ? p - N : p, ps = i < M - 1 ? p + N : p;
+          Px x;
+          x.pc = usephi ? phi[p] : 0.0;
+          x.pe = usephi ? phi[pe] : 0.0;
+          x.pw = usephi ? phi[pw] : 0.0;
+          x.pn = usephi ? phi[pn] : 0.0;
+          x.ps = usephi ? phi[ps] : 0.0;
+          x.dxc = dx[p];
+          x.dxw = dx[pw];
+          x.dyc = dy[p];
+          x.dyn = dy[pn];
+          x.uc = U[p];
+          x.uw = U[pw];
+          x.vc = V[p];
+          x.vn = V[pn];
+          return x;
+        },
+        [&](int i, int j, const Px& x) {
+          const size_t p = (size_t)i * N + j;
+          double hx = 0.0, hy = 0.0, bx = 0.0, by = 0.0, hxw = 0.0, hyn = 0.0, bxw = 0.0, byn = 0.0;
+          if (j < N - 1) {
+            const double u = (double)x.uc;
+            bx = u * x.dxc;
+            hx = usephi ? u * (x.dxc - (x.pe - x.pc)) : bx;
+          }
+          if (i < M - 1) {
+            const double v = (double)x.vc;
+            by = v * x.dyc;
+            hy = usephi ? v * (x.dyc - (x.ps - x.pc)) : by;
+          }
+          if (j > 0) {
+            const double u = (double)x.uw;
+            bxw = u * x.dxw;
+            hxw = usephi ? u * (x.dxw - (x.pc - x.pw)) : bxw;
+          }
+          if (i > 0) {
+            const double v = (double)x.vn;
+            byn = v * x.dyn;
+            hyn = usephi ? v * (x.dyn - (x.pc - x.pn)) : byn;
+          }
+          const double b = bxw + byn - bx - by;
+          const double r = hxw + hyn - hx - hy;
+          if (mode == 0) bT[p] = (T)b;
+          if (mode == 1) bT[p] = (T)r;
+          r64[p] = mode == 0 ? b : r;
+          srr += r * r;
+          sbb += b * b;
+        });
     srr = wave_sum(srr);
     sbb = wave_sum(sbb);
     if (lane_id() == 0) {
@@ -468,7 +545,7 @@ __global__ void __launch_bounds__(64) k_e_rhs(EArgs A, int mode) {
 // Small per-tile passes used by the outer loop
 // ---------------------------------------------------------------------------
 // op 0: phi_prev = phi; op 1: x0 = phi (T); op 2: x0 = 0;
-// op 3: phi += x_final (x buffer chosen by the map's l); op 4: partials of
+// op 3: phi += x_final (x[xi] plus a pending step); op 4: partials of
 // ||phi - phi_prev||^2 (slot 0) and ||phi_prev||^2 (slot 1);
 // op 5: phi = x_final (FP64 path).
 template <typename T>
@@ -487,21 +564,38 @@ __global__ void __launch_bounds__(64) k_e_pass(EArgs A, int op) {
     const T ap = (T)ms.alpha_p;
     const bool pend = ms.alpha_p != 0.0;
     double s0 = 0.0, s1 = 0.0;
-    march_points(tp, [&](int i, int j) {
-      const size_t p = (size_t)i * tp.N + j;
-      switch (op) {
-        case 0: pp[p] = phi[p]; break;
-        case 1: x0[p] = (T)phi[p]; break;
-        case 2: x0[p] = T(0); break;
-        case 3: phi[p] += (double)(pend ? xf[p] + ap * dp[p] : xf[p]); break;
-        case 4: {
-          const double dd = phi[p] - pp[p];
-          s0 += dd * dd;
-          s1 += pp[p] * pp[p];
-        } break;
-        case 5: phi[p] = (double)(pend ? xf[p] + ap * dp[p] : xf[p]); break;
-      }
-    });
+    struct Px {
+      double a, b;  // phi (ops 0, 1, 3, 4), phi_prev (op 4)
+      T x, dd;      // final iterate and pending direction (ops 3, 5)
+    };
+    march_points_grouped<4>(
+        tp,
+        [&](int i, int j) {
+          const size_t p = (size_t)i * tp.N + j;
+          Px v{0.0, 0.0, T(0), T(0)};
+          if (op == 0 || op == 1 || op == 3 || op == 4) v.a = phi[p];
+          if (op == 4) v.b = pp[p];
+          if (op == 3 || op == 5) {
+            v.x = xf[p];
+            if (pend) v.dd = dp[p];
+          }
+          return v;
+        },
+        [&](int i, int j, const Px& v) {
+          const size_t p = (size_t)i * tp.N + j;
+          switch (op) {
+            case 0: pp[p] = v.a; break;
+            case 1: x0[p] = (T)v.a; break;
+            case 2: x0[p] = T(0); break;
+            case 3: phi[p] = v.a + (double)(pend ? v.x + ap * v.dd : v.x); break;
+            case 4: {
+              const double dd = v.a - v.b;
+              s0 += dd * dd;
+              s1 += v.b * v.b;
+            } break;
+            case 5: phi[p] = (double)(pend ? v.x + ap * v.dd : v.x); break;
+          }
+        });
     if (op == 4) {
       s0 = wave_sum(s0);
       s1 = wave_sum(s1);
