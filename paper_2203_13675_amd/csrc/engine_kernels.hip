@@ -345,13 +345,26 @@ __global__ void __launch_bounds__(64) k_e_wrapdiff(EArgs A, int zero_phi) {
     double* phi = A.desc[tp.m].phi;
     double* dx = A.dx + tp.off;
     double* dy = A.dy + tp.off;
-    march_points(tp, [&](int i, int j) {
-      const size_t p = (size_t)i * tp.N + j;
-      const double c = psi[p];
-      dx[p] = (j < tp.N - 1) ? wrap_w(psi[p + 1] - c) : 0.0;
-      dy[p] = (i < tp.M - 1) ? wrap_w(psi[p + tp.N] - c) : 0.0;
-      if (zero_phi) phi[p] = 0.0;
-    });
+    struct Px {
+      double c, e, s;
+    };
+    march_points_grouped<4>(
+        tp,
+        [&](int i, int j) {
+          // neighbours outside the grid read the pixel itself (never used)
+          const size_t p = (size_t)i * tp.N + j;
+          Px x;
+          x.c = psi[p];
+          x.e = psi[j < tp.N - 1 ? p + 1 : p];
+          x.s = psi[i < tp.M - 1 ? p + tp.N : p];
+          return x;
+        },
+        [&](int i, int j, const Px& x) {
+          const size_t p = (size_t)i * tp.N + j;
+          dx[p] = (j < tp.N - 1) ? wrap_w(x.e - x.c) : 0.0;
+          dy[p] = (i < tp.M - 1) ? wrap_w(x.s - x.c) : 0.0;
+          if (zero_phi) phi[p] = 0.0;
+        });
   }
 }
 
