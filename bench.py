@@ -66,7 +66,7 @@ def measured_traffic(cls, dct_mode, maps):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--maps", type=int, default=256)
     ap.add_argument("--workload", default="batch256",
