@@ -261,7 +261,11 @@ typedef struct lpu_tuning {
     int tile_rows;        /* rows per stencil tile (one wave, 128 columns): 4, 8, 16, 32 or 64 */
     int grid;             /* blocks of the grid-stride stencil kernels: 64 .. 65536            */
     int dct_grid;         /* cap on the blocks of a DCT stage: 64 .. 65536                     */
-    int use_graph;        /* 1: issue each PCG iteration as one captured HIP graph launch      */
+    int use_graph;        /* 1: issue PCG iterations as captured HIP graphs of 8, 4, 2 and 1
+                             iterations.  The context keeps up to 64 of them across calls
+                             (keyed on launch shapes and preconditioner parameters) and
+                             drops them when its work buffers are reallocated or it is
+                             destroyed                                                      */
     int max_batch_iters;  /* iterations issued between host reads of the map states: 2 .. 1024 */
 } lpu_tuning;
 
@@ -279,7 +283,8 @@ int lp_unwrap_get_tuning(lp_unwrap_ctx* ctx, lpu_tuning* t);
  * outer iteration capped at `probe_iters` PCG iterations per map (a fixed
  * amount of work for every candidate); the maps' phi arrays are overwritten
  * (with use_phi0 = 0 semantics).  Coordinate search: tile_rows, then grid,
- * then dct_grid, then use_graph.
+ * then dct_grid, then use_graph; a candidate replaces the current choice only
+ * when it is at least 1 % faster.
  *   cache_path  text file of "key tile_rows grid dct_grid use_graph
  *               max_batch_iters" lines, or NULL.  The key covers the device
  *               name, preconditioner, precision, DCT mode and the multiset of
