@@ -91,9 +91,9 @@ def parse():
 def main():
     a = parse()
     if a.gpus != 1:
-        print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
-              "(the batch shards across GPUs by map, see the design notes)" % a.gpus,
-              file=sys.stderr)
+        print("bench.py: lp_unwrap runs on one GPU; --gpus %d is not supported "
+              "(the maps of a batch are independent, so a batch would shard across GPUs "
+              "by map)" % a.gpus, file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2203_13675_amd import synth
