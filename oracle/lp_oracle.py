@@ -23,8 +23,7 @@ unwrapping", arXiv 2203.13675) in plain, slow, vectorised numpy:
                              periodic true-residual replacement).
 * ``unwrap``              -- Algorithm 1 (outer fixed-point loop).
 
-Readings where the paper is silent or garbled (each is also listed in the
-design notes):
+Readings where the paper is silent or garbled:
 
 * Grid: M rows (index i) by N columns (index j, contiguous); "x" edges join
   (i,j)-(i,j+1), "y" edges join (i,j)-(i+1,j).  Every in-grid neighbour pair
