@@ -19,9 +19,12 @@ unwrapping", arXiv 2203.13675) in plain, slow, vectorised numpy:
                              preconditioner (the unweighted Neumann Laplacian),
                              and ILU(0), IC(0) and SSOR of the matrix taken in
                              red-black order (a change of M, not in the paper).
-* ``pcg``                 -- the inner loop of Algorithm 1 (Shewchuk's PCG with
-                             periodic true-residual replacement).
-* ``unwrap``              -- Algorithm 1 (outer fixed-point loop).
+* ``pcg``                 -- the inner loop of Algorithm 1: preconditioned CG
+                             with the true residual recomputed on a schedule
+                             (``replacement_due``) and the paper's stop test
+                             (``paper_inner_bound``).
+* ``unwrap``              -- Algorithm 1 (outer fixed-point loop), stopped by
+                             ``outer_relative_change``.
 
 Readings where the paper is silent or garbled:
 
@@ -274,6 +277,18 @@ def dct_matrix(n: int) -> np.ndarray:
     return C
 
 
+def dct2_ortho(x: np.ndarray) -> np.ndarray:
+    """C_M x C_N^T with C = dct_matrix, through scipy's O(MN log MN) DCT-II."""
+    import scipy.fft
+    return scipy.fft.dctn(x, type=2, norm="ortho")
+
+
+def dct3_ortho(y: np.ndarray) -> np.ndarray:
+    """C_M^T y C_N, the inverse of dct2_ortho (scipy's orthonormal DCT-III)."""
+    import scipy.fft
+    return scipy.fft.idctn(y, type=2, norm="ortho")
+
+
 def neumann_eigenvalues(M: int, N: int) -> np.ndarray:
     """Eigenvalues of the unit-weight Neumann 5-point Laplacian in the DCT-II basis."""
     lm = 2.0 - 2.0 * np.cos(np.pi * np.arange(M) / M)
@@ -291,6 +306,10 @@ class Preconditioner:
     V: np.ndarray
     omega: float = 1.0
     setup_info: dict = field(default_factory=dict)
+    # DCT preconditioner: "dense" multiplies by dct_matrix along each axis,
+    # "fft" calls scipy's orthonormal DCT-II / DCT-III (the same transform,
+    # O(MN log MN)); "auto" takes "fft" above 256 x 256 pixels
+    dct_impl: str = "auto"
 
     def __post_init__(self):
         if self.kind not in PRECONDITIONERS:
@@ -319,8 +338,13 @@ class Preconditioner:
             if self.base in ("ilu0", "ic0"):
                 self._factor()
         elif self.kind == "dct":
-            self.CM = dct_matrix(M)
-            self.CN = dct_matrix(N)
+            if self.dct_impl == "auto":
+                self.dct_impl = "fft" if M * N > 256 * 256 else "dense"
+            if self.dct_impl not in ("dense", "fft"):
+                raise ValueError(self.dct_impl)
+            if self.dct_impl == "dense":
+                self.CM = dct_matrix(M)
+                self.CN = dct_matrix(N)
             lam = neumann_eigenvalues(M, N)
             lam[0, 0] = 1.0
             self.inv_lam = 1.0 / lam
@@ -366,6 +390,10 @@ class Preconditioner:
             s = r.copy()
         elif k == "jacobi":
             s = r * self.inv_diag
+        elif k == "dct" and self.dct_impl == "fft":
+            Y = dct2_ortho(r)
+            Y *= self.inv_lam
+            s = dct3_ortho(Y)
         elif k == "dct":
             Y = self.CM @ r @ self.CN.T
             Y *= self.inv_lam
@@ -393,7 +421,7 @@ class Preconditioner:
 
 
 # ---------------------------------------------------------------------------
-# Algorithm 1, inner loop: Shewchuk's PCG
+# Algorithm 1, inner loop: preconditioned CG
 # ---------------------------------------------------------------------------
 @dataclass
 class PCGResult:
@@ -403,70 +431,108 @@ class PCGResult:
     relres: float
     delta0: float
     history: list
+    deltas: list = field(default_factory=list)    # delta_0, delta_1, ... (record=True)
+    iterates: list = field(default_factory=list)  # x_0, x_1, ... (record_iterates=True)
+
+
+def replacement_due(l: int, period: int) -> bool:
+    """Algorithm 1 recomputes the residual from its definition, r = b - A x, in
+    the iterations whose counter l is divisible by sqrt(MN) (read as the period
+    P = max(1, floor(sqrt(MN))), the first iteration l = 0 included)."""
+    return l % period == 0
+
+
+def paper_inner_bound(delta0: float, eps: float) -> float:
+    """Algorithm 1's inner loop continues while delta_new > eps^2 delta_0, where
+    delta = r^T M^{-1} r and delta_0 belongs to this solve's first residual."""
+    return eps * eps * delta0
+
+
+def _norm(v) -> float:
+    return math.sqrt(float(np.sum(v * v)))
+
+
+def _step_length(delta: float, d, q, l: int) -> float:
+    """alpha = delta / d^T A d (the CG step along d); d^T A d must be positive."""
+    curvature = float(np.sum(d * q))
+    if not (curvature > 0.0):
+        raise FloatingPointError("PCG breakdown: d^T A d <= 0 at l=%d" % l)
+    return delta / curvature
+
+
+def _advance_residual(U, V, b, x, r, alpha, q, l, period, confirm_below):
+    """Residual of the new iterate x.  The CG recurrence gives r - alpha A d;
+    Algorithm 1 replaces it by the true residual b - A x on its schedule
+    (``replacement_due``).  With ``confirm_below`` set (the relative-residual
+    stop rule), a recurrence value that meets the bound is replaced by the true
+    residual as well, so the stop test is always taken on b - A x."""
+    if replacement_due(l, period):
+        return b - apply_A(U, V, x)
+    r_next = r - alpha * q
+    if confirm_below is not None and _norm(r_next) <= confirm_below:
+        return b - apply_A(U, V, x)
+    return r_next
 
 
 def pcg(U, V, b, x0, M: Preconditioner, *, stop_rule: str = "relres", tol: float = 1e-6,
         eps_cg: float = 0.005, l_max: int | None = None, period: int | None = None,
-        record: bool = False) -> PCGResult:
-    """Solve A x = b (Eq. (7)) by PCG, following the inner loop of Algorithm 1.
+        record: bool = False, record_iterates: bool = False) -> PCGResult:
+    """Solve A x = b (Eq. (7)) by preconditioned CG from x0, the inner loop of
+    Algorithm 1 (warm start from the outer iterate).
 
-    stop_rule "paper": run while delta_new > eps_cg^2 * delta_0.
-    stop_rule "relres": run while ||r|| > tol * ||b||, always tested on a true
-    residual: in an iteration where the recursively updated residual first
-    meets the bound, b - A x replaces it (exactly as the periodic replacement
-    does) before the test.  The true residual replaces the recursive one
-    whenever l is a multiple of ``period`` (default floor(sqrt(MN))), l = 0
-    included."""
-    Mr, Nc = b.shape
-    n = Mr * Nc
-    if l_max is None:
-        l_max = 2 * n
-    if period is None:
-        period = max(1, math.isqrt(n))
+    Stop rules: "paper" runs while delta_new > eps_cg^2 delta_0
+    (``paper_inner_bound``); "relres" runs while ||r|| > tol ||b||, tested on a
+    true residual (``_advance_residual``).  At most l_max iterations (default
+    2MN); the residual is recomputed from its definition every ``period``
+    iterations (default floor(sqrt(MN))).
+
+    With record=True the result keeps the relative residual after each
+    iteration and the sequence delta_0, delta_1, ...; with record_iterates=True
+    also every iterate x_0, x_1, ..."""
+    n = b.size
+    l_max = 2 * n if l_max is None else l_max
+    period = max(1, math.isqrt(n)) if period is None else period
     x = np.array(x0, dtype=np.float64, copy=True)
-    bnorm = math.sqrt(float(np.sum(b * b)))
+    bnorm = _norm(b)
     r = b - apply_A(U, V, x)
-    d = M.apply(r)
-    delta_new = float(np.sum(r * d))
-    delta0 = delta_new
-    hist = []
+    s = M.apply(r)
+    delta = float(np.sum(r * s))
+    delta0 = delta
+    out = PCGResult(x, 0, True, 0.0, delta0, [])
+    if record:
+        out.deltas.append(delta)
+    if record_iterates:
+        out.iterates.append(x.copy())
     if bnorm == 0.0:
-        return PCGResult(x, 0, True, 0.0, delta0, hist)
+        return out
+    paper = stop_rule == "paper"
+    bound = paper_inner_bound(delta0, eps_cg)
+    confirm_below = None if paper else tol * bnorm
 
-    def rnorm(v):
-        return math.sqrt(float(np.sum(v * v)))
+    def satisfied(rv, dl):
+        return not (dl > bound) if paper else _norm(rv) <= tol * bnorm
 
-    def stop(rvec, dn):
-        if stop_rule == "paper":
-            return not (dn > eps_cg * eps_cg * delta0)
-        return rnorm(rvec) <= tol * bnorm
-
+    d = s
     l = 0
-    while l < l_max and not stop(r, delta_new):
+    while l < l_max and not satisfied(r, delta):
         q = apply_A(U, V, d)
-        dq = float(np.sum(d * q))
-        if not (dq > 0.0):
-            raise FloatingPointError("PCG breakdown: d^T A d <= 0 at l=%d" % l)
-        alpha = delta_new / dq
+        alpha = _step_length(delta, d, q, l)
         x = x + alpha * d
-        if l % period == 0:
-            r = b - apply_A(U, V, x)
-        else:
-            r = r - alpha * q
-            if stop_rule == "relres" and rnorm(r) <= tol * bnorm:
-                r = b - apply_A(U, V, x)      # confirm on the true residual
+        r = _advance_residual(U, V, b, x, r, alpha, q, l, period, confirm_below)
         s = M.apply(r)
-        delta_old = delta_new
-        delta_new = float(np.sum(r * s))
-        beta = delta_new / delta_old
-        d = s + beta * d
+        # the new direction is M^{-1} r made A-conjugate to the previous one
+        delta_prev, delta = delta, float(np.sum(r * s))
+        d = s + (delta / delta_prev) * d
         l += 1
         if record:
-            hist.append(rnorm(r) / bnorm)
-    rt = b - apply_A(U, V, x)
-    relres = rnorm(rt) / bnorm
-    conv = (relres <= tol) if stop_rule == "relres" else (not delta_new > eps_cg ** 2 * delta0)
-    return PCGResult(x, l, bool(conv), relres, delta0, hist)
+            out.history.append(_norm(r) / bnorm)
+            out.deltas.append(delta)
+        if record_iterates:
+            out.iterates.append(x.copy())
+    out.x, out.iters = x, l
+    out.relres = _norm(b - apply_A(U, V, x)) / bnorm
+    out.converged = bool(out.relres <= tol) if not paper else bool(not delta > bound)
+    return out
 
 
 # ---------------------------------------------------------------------------
@@ -481,12 +547,21 @@ class UnwrapResult:
     relres: list
     converged: bool
     history: list = field(default_factory=list)
+    outer_errs: list = field(default_factory=list)  # the outer error after each iteration
+
+
+def outer_relative_change(phi_next, phi) -> float:
+    """Algorithm 1's outer error ||phi^{k+1} - phi^k||_2 / ||phi^k||_2 (l2 over all
+    pixels); +inf when phi^k = 0, so a zero start never stops the loop."""
+    nrm = _norm(phi)
+    return _norm(phi_next - phi) / nrm if nrm > 0 else math.inf
 
 
 def unwrap(psi, mask=None, *, p: float = 0.0, tau: float = 0.01, precond: str = "dct",
            tol: float = 1e-6, k_max: int = 500, outer_tol: float = 1e-6, stop_rule: str = "relres",
            eps_cg: float = 0.005, l_max: int | None = None, period: int | None = None,
-           omega: float = 1.0, phi0=None, keep_history: bool = False) -> UnwrapResult:
+           omega: float = 1.0, phi0=None, keep_history: bool = False,
+           dct_impl: str = "auto") -> UnwrapResult:
     """Algorithm 1: from phi^0, recompute U, V (Eq. (6)), solve Eq. (7) by PCG with
     warm start phi^{k+1} <- phi^k, until k = k_max or the relative change
     ||phi^{k+1} - phi^k|| / ||phi^k|| <= outer_tol (outer_tol <= 0: run k_max)."""
@@ -497,18 +572,17 @@ def unwrap(psi, mask=None, *, p: float = 0.0, tau: float = 0.01, precond: str = 
     phi = np.zeros((M, N)) if phi0 is None else np.array(phi0, dtype=np.float64, copy=True)
     k = 0
     err = math.inf
-    inner, rels, hist = [], [], []
+    inner, rels, hist, errs = [], [], [], []
     converged = False
     while k < k_max:
         U, V = irls_weights(phi, dx, dy, wx, wy, p, tau)
         b = rhs(U, V, dx, dy)
-        P = Preconditioner(precond, U, V, omega=omega)
+        P = Preconditioner(precond, U, V, omega=omega, dct_impl=dct_impl)
         res = pcg(U, V, b, phi, P, stop_rule=stop_rule, tol=tol, eps_cg=eps_cg,
                   l_max=l_max, period=period)
-        nrm = math.sqrt(float(np.sum(phi * phi)))
-        diff = math.sqrt(float(np.sum((res.x - phi) ** 2)))
-        err = diff / nrm if nrm > 0 else math.inf
+        err = outer_relative_change(res.x, phi)
         phi = res.x
+        errs.append(err)
         inner.append(res.iters)
         rels.append(res.relres)
         if keep_history:
@@ -517,17 +591,18 @@ def unwrap(psi, mask=None, *, p: float = 0.0, tau: float = 0.01, precond: str = 
         if outer_tol > 0 and err <= outer_tol:
             converged = True
             break
-    return UnwrapResult(phi, k, inner, err, rels, converged, hist)
+    return UnwrapResult(phi, k, inner, err, rels, converged, hist, errs)
 
 
 # ---------------------------------------------------------------------------
 # Exact inner solves (O-exact) and reporting helpers
 # ---------------------------------------------------------------------------
 def unwrap_exact(psi, mask=None, *, p=0.0, tau=0.01, outer=10, phi0=None, inner_tol=1e-12,
-                 keep_history=False):
-    """Algorithm 1 with every inner system solved to relres <= inner_tol by IC(0)-PCG
-    (the reference for reporting errors of approximate inner solves)."""
-    return unwrap(psi, mask, p=p, tau=tau, precond="ic0", tol=inner_tol, k_max=outer,
+                 keep_history=False, precond="ic0"):
+    """Algorithm 1 with every inner system solved to relres <= inner_tol (IC(0)-PCG by
+    default; any preconditioner reaches the same solution): the reference for
+    reporting errors of approximate inner solves."""
+    return unwrap(psi, mask, p=p, tau=tau, precond=precond, tol=inner_tol, k_max=outer,
                   outer_tol=0.0, phi0=phi0, keep_history=keep_history)
 
 

@@ -464,12 +464,42 @@ def pin_normalized_error(O):
                 and math.isclose(O.normalized_error(mu, 0 * mu), 1.0))
 
 
+def pin_dct_fft_path(O):
+    """The O(MN log MN) DCT preconditioner equals the dense one (dct_matrix along
+    each axis) on grids of odd, even and unequal sides, and at 512 x 384 it
+    inverts the unit-weight Neumann Laplacian on zero-mean vectors."""
+    rng = np.random.default_rng(30)
+    ok = True
+    for M, N in ((7, 5), (24, 40), (64, 48), (130, 96)):
+        U = np.ones((M, N))
+        V = np.ones((M, N))
+        U[:, N - 1] = 0.0
+        V[M - 1, :] = 0.0
+        r = rng.normal(size=(M, N))
+        a = O.Preconditioner("dct", U, V, dct_impl="dense").apply(r)
+        b = O.Preconditioner("dct", U, V, dct_impl="fft").apply(r)
+        ok &= np.allclose(a, b, rtol=0, atol=1e-12 * np.abs(a).max())
+    M, N = 512, 384
+    U = np.ones((M, N))
+    V = np.ones((M, N))
+    U[:, N - 1] = 0.0
+    V[M - 1, :] = 0.0
+    r = rng.normal(size=(M, N))
+    r -= r.mean()
+    P = O.Preconditioner("dct", U, V)
+    ok &= P.dct_impl == "fft"
+    s = P.apply(r)
+    ok &= np.allclose(O.apply_A(U, V, s), r, rtol=0, atol=1e-10 * np.abs(r).max())
+    ok &= abs(s.mean()) < 1e-12
+    return bool(ok)
+
+
 PINS = [pin_wrap_range_and_ties, pin_wrapped_differences, pin_weights_hand_values,
         pin_normal_equations, pin_gradient_of_energy, pin_laplacian_properties,
         pin_dense_lstsq, pin_scipy_cg, pin_exact_recovery, pin_p2_dct_one_step,
         pin_dct_against_library, pin_incomplete_factorizations, pin_red_black_factorizations,
         pin_monotone_descent,
-        pin_cg_finite_termination, pin_normalized_error]
+        pin_cg_finite_termination, pin_normalized_error, pin_dct_fft_path]
 
 
 @pytest.mark.parametrize("pin", PINS, ids=lambda f: f.__name__)
@@ -495,14 +525,184 @@ def test_paper_parameters_are_the_defaults(oracle):
 
 
 def test_paper_stop_rule_and_caps(oracle):
-    """'paper' stop rule ends as soon as delta_new <= eps^2 delta_0; l_max = 1 caps
-    the inner loop after one step."""
+    """The 'paper' stop rule ends the inner loop at the first iterate with
+    delta <= eps^2 delta_0 (delta recomputed here from the iterates); l_max = 1
+    caps the inner loop after one step."""
+    assert pin_paper_inner_stop(oracle)
     M, N = 16, 16
     psi, _ = noisy_peaks(M, N, 4.0, 0.3, 15)
-    r = oracle.unwrap(psi, p=0.0, precond="jacobi", stop_rule="paper", k_max=3, outer_tol=0.0)
-    assert all(i > 0 for i in r.inner_iters[:1])
     r1 = oracle.unwrap(psi, p=0.0, precond="jacobi", l_max=1, k_max=2, outer_tol=0.0)
     assert r1.inner_iters == [1, 1]
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 1's control flow: inner stop test, residual schedule, outer error
+# ---------------------------------------------------------------------------
+def dense_system(M, N, U, V):
+    """A = D^T W D from the incidence matrix, with W the edge weights U (x edges)
+    and V (y edges); written independently of the oracle's stencil."""
+    D, E = incidence(M, N)
+    w = edge_values(E, U, V)
+    return D.T @ (w[:, None] * D)
+
+
+def pin_paper_inner_stop(O):
+    """Algorithm 1's inner test: PCG continues while delta > eps^2 delta_0, with
+    delta = r^T M^{-1} r.  For Jacobi-PCG on a random weighted grid, delta is
+    recomputed from every iterate with a dense A and diag(A): the last iterate
+    is the first whose delta is at or below eps^2 delta_0.  A mistake in the
+    bound (eps instead of eps^2) stops the loop well before that."""
+    ok = True
+    for seed, (M, N), eps in ((21, (9, 11), 0.005), (22, (12, 7), 0.05), (23, (10, 10), 0.01)):
+        rng = np.random.default_rng(seed)
+        U, V = random_weights(M, N, rng, lo=0.02)
+        A = dense_system(M, N, U, V)
+        b = rng.normal(size=M * N)
+        b -= b.mean()
+        res = O.pcg(U, V, b.reshape(M, N), np.zeros((M, N)), O.Preconditioner("jacobi", U, V),
+                    stop_rule="paper", eps_cg=eps, record_iterates=True)
+        dg = np.diag(A)
+        deltas = []
+        for x in res.iterates:
+            r = b - A @ x.ravel()
+            deltas.append(float(r @ (r / dg)))
+        bound = eps * eps * deltas[0]
+        L = res.iters
+        ok &= L >= 2 and len(deltas) == L + 1
+        ok &= deltas[L] <= bound * (1 + 1e-9)
+        ok &= all(d > bound * (1 + 1e-9) for d in deltas[:L])
+        # the case is not decided by rounding: both sides of the boundary are clear
+        ok &= abs(deltas[L] / bound - 1) > 1e-6 and abs(deltas[L - 1] / bound - 1) > 1e-6
+    return bool(ok)
+
+
+def pin_relres_stop_on_true_residual(O):
+    """The relative-residual rule ends at the first iterate whose true residual
+    ||b - A x|| (dense A here) is within tol ||b||."""
+    ok = True
+    for seed, pc in ((24, "none"), (25, "jacobi"), (26, "ilu0")):
+        rng = np.random.default_rng(seed)
+        M, N = 8, 9
+        U, V = random_weights(M, N, rng, lo=0.02)
+        A = dense_system(M, N, U, V)
+        b = rng.normal(size=M * N)
+        b -= b.mean()
+        tol = 1e-6
+        res = O.pcg(U, V, b.reshape(M, N), np.zeros((M, N)), O.Preconditioner(pc, U, V),
+                    tol=tol, record_iterates=True)
+        rel = [np.linalg.norm(b - A @ x.ravel()) / np.linalg.norm(b) for x in res.iterates]
+        ok &= rel[-1] <= tol * (1 + 1e-6) and all(v > tol for v in rel[:-1])
+    return bool(ok)
+
+
+def _call_trace(O, run):
+    """Run ``run(spy_precond)`` with the oracle's stencil product and the
+    preconditioner's apply logged: returns the sequence of 'A' / 'M' calls."""
+    events = []
+    orig = O.apply_A
+
+    def spy_A(U, V, x):
+        events.append("A")
+        return orig(U, V, x)
+
+    def wrap_precond(P):
+        inner = P.apply
+
+        def spy_M(r):
+            events.append("M")
+            return inner(r)
+        P.apply = spy_M
+        return P
+    O.apply_A = spy_A
+    try:
+        run(wrap_precond)
+    finally:
+        O.apply_A = orig
+    return events
+
+
+def pin_residual_replacement_schedule(O):
+    """Algorithm 1 recomputes r = b - A x in the iterations l divisible by the
+    period (l = 0 included).  Observed from the calls PCG makes: one stencil
+    product per iteration (A d), a second one in a replacement iteration, one
+    preconditioner apply per iteration."""
+    ok = True
+    rng = np.random.default_rng(27)
+    M, N = 6, 7
+    U, V = random_weights(M, N, rng)
+    b = rng.normal(size=(M, N))
+    b -= b.mean()
+    for L, P in ((11, 4), (10, 3), (7, 1), (9, 20)):
+        ev = _call_trace(O, lambda w: O.pcg(U, V, b, np.zeros((M, N)), w(O.Preconditioner("jacobi", U, V)),
+                                             stop_rule="paper", eps_cg=1e-30, l_max=L, period=P))
+        # r0 and s0, then per iteration A [A] M, then the final true residual
+        ok &= ev[:2] == ["A", "M"] and ev[-1] == "A"
+        body = "".join(ev[2:-1])
+        chunks = body.split("M")
+        ok &= chunks[-1] == ""
+        chunks = chunks[:-1]
+        ok &= len(chunks) == L
+        replaced = {l for l, c in enumerate(chunks) if c == "AA"}
+        ok &= all(c in ("A", "AA") for c in chunks)
+        ok &= replaced == {l for l in range(L) if l % P == 0}
+    return bool(ok)
+
+
+def pin_outer_relative_change(O):
+    """Algorithm 1's outer error ||phi^{k+1} - phi^k|| / ||phi^k||, recomputed
+    from the iterates: every reported value matches, a zero start gives an
+    infinite first error, and the loop stops at the first iteration whose error
+    is at or below the tolerance."""
+    M, N = 14, 12
+    psi, _ = noisy_peaks(M, N, 3.0, 0.3, 28)
+    phi0 = 0.05 * np.random.default_rng(29).normal(size=(M, N))
+    r = O.unwrap(psi, p=0.0, precond="ilu0", tol=1e-12, k_max=4, outer_tol=0.0,
+                 phi0=phi0, keep_history=True)
+    its = [phi0] + r.history
+    want = [np.linalg.norm(b - a) / np.linalg.norm(a) for a, b in zip(its, its[1:])]
+    ok = len(r.outer_errs) == 4 and np.allclose(r.outer_errs, want, rtol=1e-12, atol=0)
+    ok &= math.isclose(r.outer_err, want[-1], rel_tol=1e-12)
+    # from phi0 = 0 the first error is infinite
+    r0 = O.unwrap(psi, p=0.0, precond="ilu0", tol=1e-12, k_max=1, outer_tol=0.5)
+    ok &= math.isinf(r0.outer_err) and r0.outer_iters == 1 and not r0.converged
+    # stop at the first error at or below outer_tol
+    e = want
+    if e[2] < e[1]:
+        tol = math.sqrt(e[1] * e[2])
+        first = next(k for k, v in enumerate(e) if v <= tol) + 1
+        rs = O.unwrap(psi, p=0.0, precond="ilu0", tol=1e-12, k_max=10, outer_tol=tol, phi0=phi0)
+        ok &= rs.converged and rs.outer_iters == first
+    else:
+        ok = False
+    return bool(ok)
+
+
+def test_algorithm1_control_flow(oracle):
+    assert pin_paper_inner_stop(oracle)
+    assert pin_relres_stop_on_true_residual(oracle)
+    assert pin_residual_replacement_schedule(oracle)
+    assert pin_outer_relative_change(oracle)
+
+
+def test_mutation_paper_bound_eps_not_squared(oracle, monkeypatch):
+    """The inner test with eps delta_0 in place of eps^2 delta_0."""
+    _mutant(oracle, monkeypatch, "paper_inner_bound", lambda d0, eps: eps * d0)
+    assert not pin_paper_inner_stop(oracle)
+
+
+def test_mutation_outer_error_normalised_by_new_iterate(oracle, monkeypatch):
+    """The outer error divided by ||phi^{k+1}|| instead of ||phi^k||."""
+    def bad(phi_next, phi):
+        n = float(np.linalg.norm(phi_next))
+        return float(np.linalg.norm(phi_next - phi)) / n if n > 0 else math.inf
+    _mutant(oracle, monkeypatch, "outer_relative_change", bad)
+    assert not pin_outer_relative_change(oracle)
+
+
+def test_mutation_replacement_offset(oracle, monkeypatch):
+    """Replacement in the iterations with l mod P == 1 instead of 0."""
+    _mutant(oracle, monkeypatch, "replacement_due", lambda l, P: l % P == (1 % P))
+    assert not pin_residual_replacement_schedule(oracle)
 
 
 def test_one_row_map_pivot_floor(oracle):
@@ -617,3 +817,9 @@ def test_mutation_pcg_beta(oracle, monkeypatch):
     _mutant(oracle, monkeypatch, "pcg", bad_pcg)
     assert not pin_cg_finite_termination(oracle)
     monkeypatch.setattr(oracle, "pcg", src_pcg)
+
+
+def test_mutation_dct_fft_inverse_type(oracle, monkeypatch):
+    """The FFT path inverting with a DCT-II instead of the DCT-III."""
+    _mutant(oracle, monkeypatch, "dct3_ortho", oracle.dct2_ortho)
+    assert not pin_dct_fft_path(oracle)
