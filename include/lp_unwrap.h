@@ -129,10 +129,14 @@ typedef struct lpu_map {
 void lpu_default_options(lpu_options* opt);
 
 /* Create a context bound to HIP device `device` and stream `stream` (a
- * hipStream_t; NULL = the null stream).  Workspace for maps of up to
- * max_rows x max_cols is allocated now (0, 0: allocate on first use); larger
- * maps grow it.  The context owns its workspace; free it with
- * lp_unwrap_destroy.  Errors: LPU_ERR_INVALID_ARG, LPU_ERR_OOM, LPU_ERR_HIP. */
+ * hipStream_t; NULL = the null stream).  With max_rows, max_cols > 0 the work
+ * buffers for one map of up to max_rows x max_cols (either precision, the
+ * default tile height) are allocated now, so a first lp_unwrap_solve of such
+ * a map allocates only its DCT tables; 0, 0 allocates on first use.  A batch,
+ * a larger map or a smaller tile height grows the buffers (reallocation drops
+ * the context's cached graphs).  The context owns its workspace; free it
+ * with lp_unwrap_destroy.  Errors: LPU_ERR_INVALID_ARG (also for
+ * max_rows * max_cols > 2^31), LPU_ERR_OOM, LPU_ERR_HIP. */
 int lp_unwrap_create(lp_unwrap_ctx** out, int device, void* stream, int max_rows, int max_cols);
 
 /* Destroy a context and free its device memory.  NULL is ignored. */
@@ -162,7 +166,10 @@ int lp_unwrap_solve(lp_unwrap_ctx* ctx, int M, int N, const double* psi, const f
  * pointers.  Every map runs Algorithm 1 with the same p, eps, preconditioner,
  * tol and options; each map stops on its own (per-map convergence flags), and
  * every step of every iteration is one launch for all active maps.
- * Supported preconditioners: LPU_PC_NONE, LPU_PC_JACOBI, LPU_PC_DCT.
+ * Every preconditioner of lpu_preconditioner is supported.  The natural-order
+ * ILU(0) / IC(0) / SSOR sweeps are sequential along each map, so each map's
+ * sweep is walked by one workgroup; the other preconditioners are tiled over
+ * the whole device.
  * per_map: HOST array of n_maps lpu_stats, or NULL.
  * Returns the worst status over the maps (an error if any map failed). */
 int lp_unwrap_batch(lp_unwrap_ctx* ctx, int n_maps, const lpu_map* maps, double p, double eps,
@@ -175,10 +182,17 @@ const char* lp_unwrap_status_string(int status);
 const char* lp_unwrap_last_error(const lp_unwrap_ctx* ctx);
 
 /* ----------------------------------------------------------------------------
- * Single steps of the path, exposed so each kernel can be checked on its own.
- * They run exactly the kernels the solver runs.  `precision` selects the
- * element type of the weight/vector arguments typed void*: float for
- * LPU_MIXED, double for LPU_FP64.
+ * Single steps of the path, exposed so each step can be checked on its own.
+ * The wrapped differences, weights, right-hand side, pivots and the DCT, sweep
+ * and two-colour preconditioner applies run the kernels the solver runs.  Two
+ * steps run a plain kernel of their own instead of the solver's fused one:
+ * lpu_apply_A (the solver forms A d inside its fused direction-update + SpMV
+ * kernel) and the Jacobi apply of lpu_precond_apply (the solver scales r inside
+ * its fused update kernel); the fused kernels are checked through whole solves.
+ * All step calls use the context's work buffers and synchronise the stream
+ * before returning.  `precision` selects the element type of the
+ * weight/vector arguments typed void*: float for LPU_MIXED, double for
+ * LPU_FP64.
  * ------------------------------------------------------------------------- */
 
 /* Section 2.1: Delta^x_{i,j} = W(psi_{i,j+1} - psi_{i,j}) for j < N-1 and
@@ -297,6 +311,16 @@ int lp_unwrap_get_tuning(lp_unwrap_ctx* ctx, lpu_tuning* t);
 int lp_unwrap_autotune(lp_unwrap_ctx* ctx, int n_maps, const lpu_map* maps, double p, double eps,
                        int preconditioner, double tol, const lpu_options* opts, int probe_iters,
                        const char* cache_path, lpu_tuning* best, double* tune_ms);
+
+/* ----------------------------------------------------------------------------
+ * Testing hook for the failure path of Algorithm 1's inner loop: from the
+ * next solve on, the step length of PCG iteration `iteration` (1-based) of
+ * every inner solve is treated as a breakdown (as if d^T A d <= 0), so the
+ * solve returns LPU_ERR_BREAKDOWN through the same per-map state and exit as
+ * a real breakdown; every kernel still runs to completion.  iteration <= 0
+ * switches it off.  Errors: LPU_ERR_INVALID_ARG for a null context.
+ * ------------------------------------------------------------------------- */
+int lpu_debug_force_breakdown(lp_unwrap_ctx* ctx, long long iteration);
 
 #ifdef __cplusplus
 }

@@ -88,9 +88,12 @@ def build_native(force: bool = False) -> str:
 def _native():
     global _lib
     if _lib is None:
-        if not os.path.exists(_SO):
+        # LP_ORACLE_SPARSE_SO names another build of sparse_ref.c (the
+        # sanitizer test loads an address/undefined-behaviour checked one)
+        so = os.environ.get("LP_ORACLE_SPARSE_SO") or _SO
+        if so == _SO and not os.path.exists(_SO):
             build_native()
-        lib = ctypes.CDLL(_SO)
+        lib = ctypes.CDLL(so)
         ip = np.ctypeslib.ndpointer(np.int32, flags="C")
         dp = np.ctypeslib.ndpointer(np.float64, flags="C")
         lib.orc_ilu0.argtypes = [ctypes.c_int, ip, ip, dp, ctypes.c_double, dp]

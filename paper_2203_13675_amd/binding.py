@@ -8,7 +8,6 @@ library has not been built (there is no CPU fallback).
 from __future__ import annotations
 
 import ctypes
-import math
 import os
 from dataclasses import dataclass
 
@@ -71,7 +70,7 @@ EXPORTED = ["lpu_default_options", "lp_unwrap_create", "lp_unwrap_destroy", "lp_
             "lpu_wrapped_differences", "lpu_weights", "lpu_apply_A", "lpu_rhs",
             "lpu_precond_apply", "lpu_ilu_pivots", "lpu_kernel_timing", "lpu_kernel_timing_get",
             "lpu_default_tuning", "lp_unwrap_set_tuning", "lp_unwrap_get_tuning",
-            "lp_unwrap_autotune"]
+            "lp_unwrap_autotune", "lpu_debug_force_breakdown"]
 
 # kernel classes of the instrumentation (lpu_kernel_class)
 KERNEL_CLASSES = {"spmv": 0, "update": 1, "confirm": 2, "init": 3, "dct": 4, "sweep": 5,
@@ -128,6 +127,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                        ctypes.POINTER(LpuOptions), ip, ctypes.c_char_p,
                                        ctypes.POINTER(LpuTuning), ctypes.POINTER(dp)]
     lib.lp_unwrap_autotune.restype = ip
+    lib.lpu_debug_force_breakdown.argtypes = [vp, ctypes.c_longlong]
+    lib.lpu_debug_force_breakdown.restype = ip
     return lib
 
 
@@ -398,6 +399,11 @@ class Context:
                                       _ptr(dx), _ptr(dy), _ptr(b)))
         return b
 
+    def debug_force_breakdown(self, iteration: int):
+        """Testing hook: PCG iteration `iteration` of every later inner solve
+        reports a breakdown (0 switches it off)."""
+        self._raise(self._lib.lpu_debug_force_breakdown(self._h, int(iteration)))
+
     def precond_apply(self, U, V, r, preconditioner, *, precision="fp64", dct_mode="split_bf16",
                       omega=1.0):
         M, N = r.shape
@@ -415,6 +421,3 @@ class Context:
                                              _ptr(piv)))
         return piv
 
-
-def default_period(M, N):
-    return max(1, math.isqrt(M * N))

@@ -164,9 +164,24 @@ int lp_unwrap_create(lp_unwrap_ctx** out, int device, void* stream, int max_rows
     delete ctx;
     return LPU_ERR_HIP;
   }
-  (void)max_rows;
-  (void)max_cols;
+  if (max_rows > 0 && max_cols > 0) {
+    if ((long long)max_rows * max_cols > (1LL << 31)) {
+      lp_unwrap_destroy(ctx);
+      return LPU_ERR_INVALID_ARG;
+    }
+    const int rc = engine_reserve(ctx, max_rows, max_cols);
+    if (rc != LPU_OK) {
+      lp_unwrap_destroy(ctx);
+      return rc;
+    }
+  }
   *out = ctx;
+  return LPU_OK;
+}
+
+int lpu_debug_force_breakdown(lp_unwrap_ctx* ctx, long long iteration) {
+  if (!ctx) return LPU_ERR_INVALID_ARG;
+  ctx->debug_breakdown_at = iteration > 0 ? iteration : 0;
   return LPU_OK;
 }
 

@@ -313,6 +313,19 @@ static int engine_setup(lp_unwrap_ctx* ctx, int n, const lpu_map* maps, int elem
   return LPU_OK;
 }
 
+// Size the work buffers for one map of M x N in FP64 (enough for any one map
+// of at most that size in either precision, under the current tile height);
+// called by lp_unwrap_create so a first solve allocates nothing.
+int engine_reserve(lp_unwrap_ctx* ctx, int M, int N) {
+  lpu_map mp;
+  mp.rows = M;
+  mp.cols = N;
+  mp.psi = nullptr;
+  mp.mask = nullptr;
+  mp.phi = nullptr;
+  return engine_setup(ctx, 1, &mp, 8, false, kDT);
+}
+
 // Make the tile lists cover exactly the maps in `set`.
 static int engine_activate(lp_unwrap_ctx* ctx, const std::vector<int>& set, int* ntiles,
                            int* ndtiles) {
@@ -541,6 +554,7 @@ struct Pcg {
       s.stall = sizeof(T) == 4 ? 1 : 0;  // refinement follows every mixed inner solve
       const long long px = (long long)e.hdesc[set[k]].M * e.hdesc[set[k]].N;
       s.chk_gap = std::min(px, std::max(period[k], 256LL));
+      s.brk_at = ctx->debug_breakdown_at;
       s.state = kRun;
     }
     if ((rc = write_states(ctx))) return rc;

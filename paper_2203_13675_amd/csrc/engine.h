@@ -93,6 +93,7 @@ struct MapState {
   double rr_chk;               // true residual at the last stagnation checkpoint
   long long l_chk, chk_gap;    // its iteration; least iterations between compared checkpoints
   long long l, l_max, period, nfinish;
+  long long brk_at;            // > 0: report iteration brk_at's d^T A d as a breakdown (testing hook)
   int state, rule, replaced, stall;  // stall: 1 = stop when the true residual stagnates
   int xi, pad_;                // x[xi] holds the iterate (up to the pending term)
   float amax[4];

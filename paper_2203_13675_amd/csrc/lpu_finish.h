@@ -160,7 +160,8 @@ __device__ inline void finish_map(const MapDesc* __restrict__ desc, MapState* ms
     case kFinAlpha:
       s.alpha_p = 0.0;  // every tile of the SpMV has added the pending term
       s.dq = v[0];
-      if (!(v[0] > 0.0) || !isfinite(v[0])) s.state = kBreakdown;
+      if (!(v[0] > 0.0) || !isfinite(v[0]) || (s.brk_at > 0 && s.l + 1 >= s.brk_at))
+        s.state = kBreakdown;
       else s.alpha = s.delta_new / v[0];
       break;
     case kFinUpdate: {

@@ -125,6 +125,7 @@ struct lp_unwrap_ctx {
   hipEvent_t list_event = nullptr;  // last upload from the pinned list staging
   bool list_event_live = false;
   lpu::KTimer kt;
+  long long debug_breakdown_at = 0;  // lpu_debug_force_breakdown (0: off)
 };
 
 namespace lpu {
@@ -146,6 +147,7 @@ void release_graphs(lp_unwrap_ctx* ctx);
 int engine_solve(lp_unwrap_ctx* ctx, int n, const lpu_map* maps, double p, double tau, int pc,
                  double tol, const lpu_options& o, lpu_stats* stats);
 void engine_release(lp_unwrap_ctx* ctx);
+int engine_reserve(lp_unwrap_ctx* ctx, int M, int N);
 int step_wrapdiff(lp_unwrap_ctx* ctx, int M, int N, const double* psi, double* dx, double* dy);
 template <typename T>
 int step_weights(lp_unwrap_ctx* ctx, int M, int N, const double* phi, const double* dx,

@@ -348,6 +348,53 @@ def test_iteration_caps(ctx):
     assert res.status == binding.NOT_CONVERGED and res.stats["outer_iters"] == 1
 
 
+@pytest.mark.parametrize("pc,precision", [("dct", "fp64"), ("jacobi", "fp64"), ("dct", "mixed"),
+                                          ("ilu0", "fp64"), ("ssor_rb", "mixed")])
+def test_breakdown_status(ctx, pc, precision):
+    """A PCG breakdown (d^T A d <= 0) ends the solve with LPU_ERR_BREAKDOWN and
+    a message, through the finisher's normal exit (forced from the host at a
+    chosen iteration; every kernel completes); the next solve is unaffected."""
+    from paper_2203_13675_amd import binding
+    psi, _, _ = synth.workload("peaks64")
+    ctx.debug_force_breakdown(3)
+    try:
+        res = ctx.solve(dev(psi), preconditioner=pc, precision=precision, k_max=3,
+                        outer_tol=0.0, check=False)
+        assert res.status == binding.ERR_BREAKDOWN, res
+        assert res.stats["status"] == binding.ERR_BREAKDOWN
+        assert "breakdown" in ctx.last_error().lower()
+        assert 1 <= res.stats["inner_iters_total"] <= 3
+        phis, rc, stats = ctx.batch([dev(psi), dev(psi[:40, :48].copy())], preconditioner=pc,
+                                    precision=precision, k_max=2, outer_tol=0.0, check=False)
+        assert rc == binding.ERR_BREAKDOWN and all(s["status"] == rc for s in stats)
+    finally:
+        ctx.debug_force_breakdown(0)
+    ok = ctx.solve(dev(psi), preconditioner=pc, precision=precision, k_max=3, outer_tol=0.0)
+    assert ok.status == binding.OK and ok.stats["final_relres"] <= 1e-6
+
+
+def test_create_reserves_workspace():
+    """lp_unwrap_create with max_rows x max_cols sizes the work buffers up
+    front; solves of that size and smaller then run as before, a product above
+    2^31 is refused."""
+    from paper_2203_13675_amd import binding
+    from paper_2203_13675_amd.binding import Context
+    psi, _, _ = synth.workload("peaks64")
+    with Context(0, max_rows=512, max_cols=384) as c:
+        a = c.solve(dev(psi), preconditioner="dct", precision="fp64", k_max=2, outer_tol=0.0)
+        b = c.solve(dev(psi), preconditioner="dct", precision="mixed", k_max=2, outer_tol=0.0)
+        assert a.status == 0 and b.status == 0
+        big, _ = synth.peaks_map(512, 384, scale=3.0, sigma=0.2, seed=5)
+        r = c.solve(dev(big), preconditioner="jacobi", precision="fp64", k_max=1, outer_tol=0.0)
+        assert r.stats["final_relres"] <= 1e-6
+    with Context(0) as c:
+        a2 = c.solve(dev(psi), preconditioner="dct", precision="fp64", k_max=2, outer_tol=0.0)
+    assert np.array_equal(host(a.phi), host(a2.phi))
+    h = binding.ctypes.c_void_p()
+    lib = binding.lib()
+    assert lib.lp_unwrap_create(binding.ctypes.byref(h), 0, None, 65536, 65537) == binding.ERR_INVALID_ARG
+
+
 def test_outer_convergence_stops_early(ctx, oracle):
     """With the paper's outer test (tol 1e-6 on the relative change) the loop
     stops at the fixed point, as the oracle does."""
