@@ -30,6 +30,7 @@ __all__ = [
     "hole_mask",
     "batch_sizes",
     "batch_maps",
+    "batch_map",
     "random_phi0",
     "WORKLOADS",
     "workload",
@@ -140,6 +141,15 @@ def batch_maps(n_maps: int = 256, seed: int = 3000, sides=None):
         sig = float(rng.uniform(0.1, 0.8))
         out.append(gaussians_map(M, N, sigma=sig, seed=seed + 10 + k))
     return out
+
+
+def batch_map(k: int, n_maps: int = 256, seed: int = 3000):
+    """Map k of ``batch_maps(n_maps, seed)`` alone (same shape, noise level and
+    phase), without generating the others.  Returns (psi, phi_true)."""
+    M, N = batch_sizes(n_maps, seed)[k]
+    rng = np.random.default_rng(seed + 1)
+    sig = float(rng.uniform(0.1, 0.8, k + 1)[k])
+    return gaussians_map(M, N, sigma=sig, seed=seed + 10 + k)
 
 
 def random_phi0(M: int, N: int, seed: int = 0) -> np.ndarray:
