@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblp_unwrap.so")
-SOURCES = ["engine_kernels.hip", "engine_dct.hip", "driver.hip", "dct_tables.hip", "util.hip", "capi.hip",
+SOURCES = ["engine_kernels.hip", "engine_dct.hip", "engine_sweep.hip", "driver.hip", "dct_tables.hip", "util.hip", "capi.hip",
            "autotune.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

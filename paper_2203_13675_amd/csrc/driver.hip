@@ -38,12 +38,13 @@ void e_dct_stage(hipStream_t st, const Engine& e, int ndtiles, int stage, int ex
                  const void* X, void* Out, const void* rvec, int fin_mode);
 int egrid(const Engine& e, int ntiles);
 int dct_grid_for(const Engine& e, int ndtiles);
-template <typename T> void e_pivots(hipStream_t, const Engine&, int, int, bool, double);
+template <typename T> void e_pivots(hipStream_t, const Engine&, int, bool, double);
+void wf_shape(int M, int N, int* diags, int* len);
 template <typename T> void e_tc_pivots(hipStream_t, const Engine&, int, bool, double);
 template <typename T>
 void e_twocolor(hipStream_t, const Engine&, int, int, bool, double, int);
 template <typename T>
-void e_sweep(hipStream_t, const Engine&, int, int, int, bool, double, const void*, void*, void*);
+void e_sweep(hipStream_t, const Engine&, int, int, bool, double, const void*, void*, void*);
 
 enum { kIdle = 99 };
 enum FinOpH { kFinInitH = 0, kFinAlphaH = 1, kFinUpdateH = 2, kFinConfirmH = 3, kFinTailH = 4,
@@ -147,7 +148,7 @@ static int engine_setup(lp_unwrap_ctx* ctx, int n, const lpu_map* maps, int elem
   Engine& e = ctx->eng;
   std::vector<MapDesc> hd(n);
   long long px = 0;
-  int tiles = 0, dtiles = 0, maxN = 1, groups = 0;
+  int tiles = 0, dtiles = 0, maxN = 1, groups = 0, wfd = 1, wfl = 1;
   for (int m = 0; m < n; ++m) {
     MapDesc& d = hd[m];
     std::memset(&d, 0, sizeof(d));
@@ -174,6 +175,10 @@ static int engine_setup(lp_unwrap_ctx* ctx, int n, const lpu_map* maps, int elem
     d.phi = maps[m].phi;
     d.use_iso = maps[m].mask != nullptr ? 1 : 0;
     maxN = std::max(maxN, d.N);
+    int dg = 1, ln = 1;
+    wf_shape(d.M, d.N, &dg, &ln);
+    wfd = std::max(wfd, dg);
+    wfl = std::max(wfl, ln);
     if (need_dct) {
       int stt = 0;
       d.tabM = dct_dev(ctx, d.M, &stt);
@@ -249,6 +254,8 @@ static int engine_setup(lp_unwrap_ctx* ctx, int n, const lpu_map* maps, int elem
   e.total_tiles = tiles;
   e.total_dtiles = dtiles;
   e.max_n = maxN;
+  e.wf_diags = wfd;
+  e.wf_len = wfl;
   e.th = ctx->tune.tile_rows;
   e.grid = ctx->tune.grid;
   e.dct_grid = ctx->tune.dct_grid;
@@ -457,15 +464,15 @@ struct Pcg {
       }
     } else {
       const int ev = kt.begin(LPU_KC_SWEEP, st);
-      e_sweep<T>(st, e, nmaps, e.max_n, expect, pc == kPcSsor, omega, e.r, e.s, e.t1);
+      e_sweep<T>(st, e, nmaps, expect, pc == kPcSsor, omega, e.r, e.s, e.t1);
       kt.end(ev, LPU_KC_SWEEP, st);
     }
     if (!fused) fin(st, kFinTailH, expect, mode);
   }
 
   void fin(hipStream_t st, int op, int expect, int mode = kFinishNone) {
-    const bool single = !(pc == kPcDct);
-    e_finish(st, ctx->eng, op, expect, mode, pointwise(), single);
+    // the preconditioner partials of r^T s: one per DCT or sweep tile
+    e_finish(st, ctx->eng, op, expect, mode, pointwise(), false);
   }
 
   // One PCG iteration for every running map of the active set (Algorithm 1's
@@ -496,8 +503,8 @@ struct Pcg {
       return LPU_OK;
     }
     const Engine& e = ctx->eng;
-    // the natural-order sweeps launch one block per map; every other kernel's
-    // shape depends on the tile counts only
+    // the natural-order sweeps launch one grid per tile anti-diagonal over the
+    // active maps; every other kernel's shape depends on the tile counts only
     const bool sweep = !pointwise() && !two_colour(pc) && pc != kPcDct;
     // every launch argument that is not a fixed buffer address
     int om[2] = {0, 0};
@@ -505,7 +512,8 @@ struct Pcg {
     for (int chunk = 8; chunk >= 1; chunk >>= 1) {
       if (K < chunk) continue;
       const int key[kGraphKey] = {egrid(e, nt), pointwise() ? 0 : dct_grid_for(e, nd),
-                                  sweep ? nm : 0, sweep ? e.max_n : 0, pc, dct_kind,
+                                  sweep ? nm : 0, sweep ? (e.wf_diags << 16) | e.wf_len : 0,
+                                  pc, dct_kind,
                                   (int)sizeof(T), e.th, om[0], om[1], chunk};
       hipGraphExec_t ex = nullptr;
       for (const GraphEntry& g : ctx->graphs)
@@ -639,8 +647,9 @@ static int run_maps(lp_unwrap_ctx* ctx, int n, const lpu_map* maps, double p, do
   const double t_start = now_ms();
   hipStream_t st = ctx->stream;
   const bool mixed = sizeof(T) == 4;
+  // 64 x 64 DCT tiles double as the sweeps' tiles (one partial of r^T s each)
   int rc = engine_setup(ctx, n, maps, (int)sizeof(T), pc == kPcDct,
-                        even_odd_ok(maps, n, mixed, o.dct_mode) ? 128 : kDT);
+                        pc == kPcDct && even_odd_ok(maps, n, mixed, o.dct_mode) ? 128 : kDT);
   if (rc) return rc;
   Engine& e = ctx->eng;
   KTimer& kt = ctx->kt;
@@ -750,7 +759,7 @@ static int run_maps(lp_unwrap_ctx* ctx, int n, const lpu_map* maps, double p, do
     e_weights<T>(st, e, nt, p, tau);
     if (need_diag || any_mask) e_diag<T>(st, e, nt, need_diag);
     if (pc == kPcIlu || pc == kPcIc || pc == kPcSsor)
-      e_pivots<T>(st, e, (int)act.size(), e.max_n, pc == kPcSsor, o.ssor_omega);
+      e_pivots<T>(st, e, (int)act.size(), pc == kPcSsor, o.ssor_omega);
     else if (two_colour(pc))
       e_tc_pivots<T>(st, e, nt, pc == kPcSsorRb, o.ssor_omega);
     kt.end(ev, LPU_KC_SETUP, st);
@@ -973,7 +982,7 @@ int step_pivots(lp_unwrap_ctx* ctx, int M, int N, const T* U, const T* V, T* piv
   Engine& e = ctx->eng;
   const size_t b = (size_t)M * N * sizeof(T);
   if ((rc = copy_in(ctx, e.U, U, b)) || (rc = copy_in(ctx, e.V, V, b))) return rc;
-  e_pivots<T>(ctx->stream, e, 1, N, ssor, omega);
+  e_pivots<T>(ctx->stream, e, 1, ssor, omega);
   if ((rc = copy_in(ctx, piv, e.aux, b))) return rc;
   LPU_HIP_CHECK(ctx, hipStreamSynchronize(ctx->stream));
   return LPU_OK;
@@ -1027,8 +1036,8 @@ int step_precond(lp_unwrap_ctx* ctx, int M, int N, int pc, int dct_mode, double 
     ctx->kt.end(ev, LPU_KC_TWOCOLOR, st);
     if ((rc = copy_in(ctx, s, e.s, b))) return rc;
   } else {
-    e_pivots<T>(st, e, 1, N, pc == kPcSsor, omega);
-    e_sweep<T>(st, e, 1, N, kRun, pc == kPcSsor, omega, e.r, e.s, e.t1);
+    e_pivots<T>(st, e, 1, pc == kPcSsor, omega);
+    e_sweep<T>(st, e, 1, kRun, pc == kPcSsor, omega, e.r, e.s, e.t1);
     if ((rc = copy_in(ctx, s, e.s, b))) return rc;
   }
   LPU_HIP_CHECK(ctx, hipStreamSynchronize(st));

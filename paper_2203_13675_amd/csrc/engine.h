@@ -104,7 +104,9 @@ struct Engine {
   int n_maps = 0, cap_maps = 0;
   long long total_px = 0, cap_px = 0;
   int total_tiles = 0, total_dtiles = 0, cap_tiles = 0, cap_dtiles = 0;
-  int max_n = 1;             // widest map (sweep kernels)
+  int max_n = 1;             // widest map
+  int wf_diags = 1, wf_len = 1;  // natural-order sweeps: most 64 x 64 tile anti-diagonals of a
+                                 // map, and most tiles on one anti-diagonal
   int th = kTH;              // stencil tile height (rows)
   int grid = kEngineGrid;    // cap on the blocks of the stencil tile kernels
   int dct_grid = kDctGrid;   // cap on the blocks of a DCT stage (multiple of 8)

@@ -1,5 +1,4 @@
-// Batched preconditioner kernels: the DCT Poisson solve (grouped contractions
-// over all active maps) and the natural-order sweeps (one workgroup per map).
+// Batched DCT Poisson preconditioner: grouped contractions over all active maps.
 //
 // DCT (s = L0^+ r, L0 the unit-weight Neumann Laplacian):
 //   s = C_M^T [ (C_M r C_N^T) ./ Lambda ] C_N,
@@ -739,258 +738,5 @@ void e_dct_stage(hipStream_t st, const Engine& e, int ndtiles, int stage, int ex
   else if (stage == 2) hipLaunchKernelGGL((k_e_dct_eo<0, 1, 1, 1>), dim3(grid), dim3(256), 0, st, a);
   else hipLaunchKernelGGL((k_e_dct_eo<0, 1, 1, 0>), dim3(grid), dim3(256), 0, st, a);
 }
-
-// ---------------------------------------------------------------------------
-// Sweeps: one workgroup of 1024 threads per active map
-// ---------------------------------------------------------------------------
-constexpr int kSweepT = 1024;
-
-struct SArgs {
-  const MapDesc* desc;
-  MapState* ms;
-  const int* mact;
-  const int* counts;
-  double* P;
-  long long pstride;
-  const void *U, *V, *piv, *r;
-  void *s, *y;
-  int expect;
-  int ssor;
-  double omega;
-};
-
-// pivots: skewed wavefront, thread t owns row t of a chunk of rows
-template <typename T>
-__global__ void __launch_bounds__(kSweepT) k_e_pivots(SArgs a) {
-  extern __shared__ unsigned char smem_raw[];
-  if ((int)blockIdx.x >= a.counts[2]) return;
-  const int m = a.mact[blockIdx.x];
-  const MapDesc& d = a.desc[m];
-  const int M = d.M, N = d.N;
-  const T* U = reinterpret_cast<const T*>(a.U) + d.off;
-  const T* V = reinterpret_cast<const T*>(a.V) + d.off;
-  T* piv = reinterpret_cast<T*>(const_cast<void*>(a.piv)) + d.off;
-  T* prevrow = reinterpret_cast<T*>(smem_raw);
-  T* xch = prevrow + N;
-  const int tid = threadIdx.x, nt = blockDim.x;
-  if (a.ssor) {
-    for (int p = tid; p < M * N; p += nt) {
-      const int i = p / N, j = p % N;
-      const T dg = (j > 0 ? U[p - 1] : T(0)) + U[p] + (i > 0 ? V[p - N] : T(0)) + V[p];
-      piv[p] = dg == T(0) ? T(1) : dg / (T)a.omega;
-    }
-    return;
-  }
-  for (int rb = 0; rb < M; rb += nt) {
-    const int rows = min(nt, M - rb);
-    const int i = rb + tid;
-    T pleft = T(1), uleft = T(0);
-    const int steps = rows + N - 1;
-    for (int s = 0; s < steps; ++s) {
-      const int j = s - tid;
-      T pv = T(0);
-      if (tid < rows && j >= 0 && j < N) {
-        const size_t p = (size_t)i * N + j;
-        const T uc = U[p], vc = V[p];
-        const T vn = (i > 0) ? V[p - N] : T(0);
-        const T av = uleft + uc + vn + vc;
-        if (av == T(0)) {
-          pv = T(1);
-        } else {
-          T v = av;
-          if (j > 0) v -= uleft * uleft / pleft;
-          if (i > 0) {
-            const T pup = (tid == 0) ? prevrow[j] : xch[((s - 1) & 1) * nt + tid - 1];
-            v -= vn * vn / pup;
-          }
-          if (v < (T)kPivotFloor * av) v = av;
-          pv = v;
-        }
-        piv[p] = pv;
-        pleft = pv;
-        uleft = uc;
-        if (tid == nt - 1) prevrow[j] = pv;
-      }
-      xch[(s & 1) * nt + tid] = pv;
-      __syncthreads();
-    }
-    __syncthreads();
-  }
-}
-
-template <typename T, bool REV>
-__device__ __forceinline__ T block_affine_excl(T A, T C, T* sA, T* sC) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const T Ap = REV ? __shfl_down(A, off, 64) : __shfl_up(A, off, 64);
-    const T Cp = REV ? __shfl_down(C, off, 64) : __shfl_up(C, off, 64);
-    const bool has = REV ? (lane + off < 64) : (lane >= off);
-    if (has) {
-      A = A + C * Ap;
-      C = C * Cp;
-    }
-  }
-  T Ae = REV ? __shfl_down(A, 1, 64) : __shfl_up(A, 1, 64);
-  T Ce = REV ? __shfl_down(C, 1, 64) : __shfl_up(C, 1, 64);
-  if (REV ? (lane == 63) : (lane == 0)) {
-    Ae = T(0);
-    Ce = T(1);
-  }
-  __syncthreads();
-  if (REV ? (lane == 0) : (lane == 63)) {
-    sA[w] = A;
-    sC[w] = C;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    T aa = T(0), cc = T(1);
-    for (int k = 0; k < nw; ++k) {
-      const int ww = REV ? (nw - 1 - k) : k;
-      const T ta = sA[ww], tc = sC[ww];
-      sA[ww] = aa;
-      sC[ww] = cc;
-      aa = ta + tc * aa;
-      cc = tc * cc;
-    }
-  }
-  __syncthreads();
-  return Ae + Ce * sA[w];
-}
-
-// forward (P + L) y = r, backward (P + L^T) z = P y, s = scale z; partial r.s
-template <typename T, int EPT>
-__global__ void __launch_bounds__(kSweepT) k_e_sweep(SArgs a) {
-  __shared__ T sA[kSweepT / 64], sC[kSweepT / 64];
-  __shared__ double red[kSweepT / 64];
-  if ((int)blockIdx.x >= a.counts[2]) return;
-  const int m = a.mact[blockIdx.x];
-  if (a.expect >= 0 && a.ms[m].state != a.expect) return;
-  const MapDesc& d = a.desc[m];
-  const int M = d.M, N = d.N;
-  const T* U = reinterpret_cast<const T*>(a.U) + d.off;
-  const T* V = reinterpret_cast<const T*>(a.V) + d.off;
-  const T* piv = reinterpret_cast<const T*>(a.piv) + d.off;
-  const T* r = reinterpret_cast<const T*>(a.r) + d.off;
-  T* s = reinterpret_cast<T*>(a.s) + d.off;
-  T* y = reinterpret_cast<T*>(a.y) + d.off;
-  const T scale = a.ssor ? (T)(2.0 - a.omega) : T(1);
-  const int j0 = threadIdx.x * EPT;
-  T prev[EPT];
-#pragma unroll
-  for (int e = 0; e < EPT; ++e) prev[e] = T(0);
-  for (int i = 0; i < M; ++i) {
-    T av[EPT], cv[EPT];
-    T SA = T(0), SC = T(1);
-#pragma unroll
-    for (int e = 0; e < EPT; ++e) {
-      const int j = j0 + e;
-      if (j < N) {
-        const size_t p = (size_t)i * N + j;
-        const T pp = piv[p];
-        const T vn = i > 0 ? V[p - N] : T(0);
-        const T uw = j > 0 ? U[p - 1] : T(0);
-        av[e] = (r[p] + vn * prev[e]) / pp;
-        cv[e] = uw / pp;
-      } else {
-        av[e] = T(0);
-        cv[e] = T(0);
-      }
-      SA = av[e] + cv[e] * SA;
-      SC = cv[e] * SC;
-    }
-    T yin = block_affine_excl<T, false>(SA, SC, sA, sC);
-#pragma unroll
-    for (int e = 0; e < EPT; ++e) {
-      yin = av[e] + cv[e] * yin;
-      prev[e] = yin;
-      if (j0 + e < N) y[(size_t)i * N + j0 + e] = yin;
-    }
-  }
-#pragma unroll
-  for (int e = 0; e < EPT; ++e) prev[e] = T(0);
-  double part = 0.0;
-  for (int i = M - 1; i >= 0; --i) {
-    T av[EPT], cv[EPT];
-    T SA = T(0), SC = T(1);
-#pragma unroll
-    for (int e = EPT - 1; e >= 0; --e) {
-      const int j = j0 + e;
-      if (j < N) {
-        const size_t p = (size_t)i * N + j;
-        const T pp = piv[p];
-        av[e] = y[p] + V[p] * prev[e] / pp;
-        cv[e] = U[p] / pp;
-      } else {
-        av[e] = T(0);
-        cv[e] = T(0);
-      }
-      SA = av[e] + cv[e] * SA;
-      SC = cv[e] * SC;
-    }
-    T zin = block_affine_excl<T, true>(SA, SC, sA, sC);
-#pragma unroll
-    for (int e = EPT - 1; e >= 0; --e) {
-      const int j = j0 + e;
-      zin = av[e] + cv[e] * zin;
-      prev[e] = zin;
-      if (j < N) {
-        const size_t p = (size_t)i * N + j;
-        const T sv = scale * zin;
-        s[p] = sv;
-        part += (double)r[p] * (double)sv;
-      }
-    }
-  }
-  double v[1] = {part};
-  block_sum<1>(v, red);
-  if (threadIdx.x == 0) a.P[1 * a.pstride + d.dtile0] = v[0];
-}
-
-static SArgs make_sargs(const Engine& e, int expect, bool ssor, double omega, const void* r,
-                        void* s, void* y) {
-  SArgs a;
-  a.desc = e.desc;
-  a.ms = e.ms;
-  a.mact = e.mact;
-  a.counts = e.counts;
-  a.P = e.P;
-  a.pstride = e.pstride;
-  a.U = e.U;
-  a.V = e.V;
-  a.piv = e.aux;
-  a.r = r;
-  a.s = s;
-  a.y = y;
-  a.expect = expect;
-  a.ssor = ssor ? 1 : 0;
-  a.omega = omega;
-  return a;
-}
-
-template <typename T>
-void e_pivots(hipStream_t st, const Engine& e, int nmaps, int maxN, bool ssor, double omega) {
-  const size_t shm = (size_t)maxN * sizeof(T) + 2 * kSweepT * sizeof(T);
-  hipLaunchKernelGGL(k_e_pivots<T>, dim3(std::max(1, nmaps)), dim3(kSweepT), shm, st,
-                     make_sargs(e, -1, ssor, omega, nullptr, nullptr, nullptr));
-}
-
-template <typename T>
-void e_sweep(hipStream_t st, const Engine& e, int nmaps, int maxN, int expect, bool ssor,
-             double omega, const void* r, void* s, void* y) {
-  const SArgs a = make_sargs(e, expect, ssor, omega, r, s, y);
-  const int ept = (maxN + kSweepT - 1) / kSweepT;
-  const dim3 g(std::max(1, nmaps));
-  if (ept <= 1) hipLaunchKernelGGL((k_e_sweep<T, 1>), g, dim3(kSweepT), 0, st, a);
-  else if (ept <= 2) hipLaunchKernelGGL((k_e_sweep<T, 2>), g, dim3(kSweepT), 0, st, a);
-  else hipLaunchKernelGGL((k_e_sweep<T, 4>), g, dim3(kSweepT), 0, st, a);
-}
-
-template void e_pivots<float>(hipStream_t, const Engine&, int, int, bool, double);
-template void e_pivots<double>(hipStream_t, const Engine&, int, int, bool, double);
-template void e_sweep<float>(hipStream_t, const Engine&, int, int, int, bool, double, const void*,
-                             void*, void*);
-template void e_sweep<double>(hipStream_t, const Engine&, int, int, int, bool, double, const void*,
-                              void*, void*);
 
 }  // namespace lpu
