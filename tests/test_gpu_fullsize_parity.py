@@ -1,0 +1,255 @@
+"""The unwrapped phase at full size against the oracle's own answers.
+
+The oracle runs Algorithm 1 on the full-size workloads once, from
+``tests/golden/make_fullsize_oracle.py`` (a script that calls only
+``oracle/``), into ``tests/golden/fullsize_cache/``; these tests skip when that
+cache has not been written.  Every comparison is element by element with the
+mean over the valid pixels removed (the solution is unique up to a constant),
+on the whole grid at 1024^2 and on the strided sample the cache keeps at
+2048^2 (every 2nd pixel) and 4096^2 (every 4th).
+
+* FP64 path, 1024^2 peaks, p in {0, 1}, DCT / Jacobi / ILU(0), ten outer
+  iterations with the relative-residual stop rule: the oracle running the same
+  algorithm.  Bound: 50 x the distance the oracle's own answer moves under a
+  1e-14 relative perturbation of psi (the stop test can fall one iteration
+  apart under different rounding), at least 1e-6 rad; inner iteration totals
+  within 10 + 3 %.
+* FP64 path, fixed work (40 PCG iterations per inner solve, three outer
+  iterations, no stop test), six preconditioners: the same work in the oracle,
+  to 1e-9 of max |phi|.
+* Mixed path: against exact inner solves (relres 1e-12), within
+  max(3 x the error the FP64 oracle makes at the same tolerance, 1e-4 rad);
+  at 1024^2 also at the inner tolerance where the FP64 oracle itself is well
+  inside 1e-4 rad, held to 1e-4 rad.
+* The 256-map batch: one square map of each side length against exact inner
+  solves over ten outer iterations (same bound), and every map's residual after
+  one outer step assembled by the oracle.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from paper_2203_13675_amd import synth  # noqa: E402
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CACHE = os.path.join(HERE, "golden", "fullsize_cache")
+TOL = 1e-6
+TARGET_RAD = 1e-4
+BATCH_REPS = {128: 33, 256: 7, 384: 19, 512: 105, 768: 23, 1024: 22}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2203_13675_amd.binding import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def dev(a, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda", dtype)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.double().cpu().numpy()
+
+
+class Cached:
+    def __init__(self, key):
+        path = os.path.join(CACHE, key + ".npz")
+        if not os.path.exists(path):
+            pytest.skip("oracle cache %s missing: run python tests/golden/make_fullsize_oracle.py" % key)
+        z = np.load(path)
+        self.info = json.loads(str(z["info"]))
+        self.diff = float(z["diff"]) if "diff" in z else None
+        if "phi" in z:
+            self.phi = z["phi"]
+            self.stride = int(z["stride"])
+            self.mean = float(z["mean"])
+            self.valid = z["valid"]
+
+    def compare(self, phi_full, valid_full):
+        """max |(phi - mean) - (oracle - mean)| over the valid pixels of the sample."""
+        st = self.stride
+        mine = phi_full[::st, ::st] - phi_full[valid_full].mean()
+        ref = self.phi - self.mean
+        v = self.valid
+        assert np.array_equal(v, valid_full[::st, ::st])
+        return float(np.abs(mine[v] - ref[v]).max())
+
+    def dist(self, other):
+        """The same distance between two cached answers on one sample."""
+        assert self.stride == other.stride
+        v = self.valid
+        return float(np.abs((self.phi - self.mean)[v] - (other.phi - other.mean)[v]).max())
+
+
+def valid_pixels(oracle, psi, mask):
+    wx, wy = oracle.edge_quality(mask, *psi.shape)
+    return ~oracle.isolated_pixels(wx, wy)
+
+
+def inputs(workload):
+    if workload.startswith("batch256:"):
+        psi, _ = synth.batch_map(int(workload.split(":")[1]))
+        return psi, None
+    psi, mask, _ = synth.workload(workload)
+    return psi, mask
+
+
+def sensitivity(base):
+    return max(Cached("%s_perturbed%d" % (base, s)).diff for s in range(3))
+
+
+# ---------------------------------------------------------------------------
+# 1024 x 1024 peaks: FP64 path against the oracle's same algorithm
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("pc", ["dct", "jacobi", "ilu0"])
+@pytest.mark.parametrize("p", [0, 1])
+def test_peaks1024_fp64_matches_oracle(ctx, oracle, pc, p):
+    base = "peaks1024_same_%s_p%d" % (pc, p)
+    ref = Cached(base)
+    sens = sensitivity(base)
+    psi, mask = inputs("peaks1024")
+    res = ctx.solve(dev(psi), p=float(p), preconditioner=pc, tol=TOL, precision="fp64",
+                    k_max=10, outer_tol=0.0)
+    phi = host(res.phi)
+    d = ref.compare(phi, valid_pixels(oracle, psi, mask))
+    inner_o = sum(ref.info["inner_iters"])
+    inner_g = res.stats["inner_iters_total"]
+    print("peaks1024 fp64 %s p=%d: max |phi - oracle| %.3e (oracle sensitivity %.3e); inner "
+          "iterations gpu %d oracle %d %s" % (pc, p, d, sens, inner_g, inner_o,
+                                              ref.info["inner_iters"]))
+    assert res.stats["outer_iters"] == 10
+    assert res.stats["final_relres"] <= TOL
+    assert abs(inner_g - inner_o) <= 10 + 0.03 * inner_o
+    assert d <= max(1e-6, 50.0 * sens)
+
+
+@pytest.mark.parametrize("pc", ["none", "jacobi", "ilu0", "ic0", "ssor", "dct"])
+def test_peaks1024_fp64_fixed_work(ctx, oracle, pc):
+    ref = Cached("peaks1024_fixed_%s_p0" % pc)
+    psi, mask = inputs("peaks1024")
+    res = ctx.solve(dev(psi), p=0.0, preconditioner=pc, precision="fp64", stop_rule="paper",
+                    eps_cg=1e-30, l_max=40, k_max=3, outer_tol=0.0, check=False)
+    assert res.stats["inner_iters_total"] == 120
+    phi = host(res.phi)
+    d = ref.compare(phi, valid_pixels(oracle, psi, mask))
+    scale = float(np.abs(ref.phi).max())
+    print("peaks1024 fp64 fixed work %s: max |phi - oracle| %.3e (max |phi| %.1f)" % (pc, d, scale))
+    assert d <= 1e-9 * scale
+
+
+# ---------------------------------------------------------------------------
+# 1024 x 1024 peaks: mixed path against exact inner solves
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("pc,mode", [("dct", "split_bf16"), ("dct", "fp16_scaled"),
+                                     ("jacobi", "split_bf16"), ("ilu0", "split_bf16")])
+@pytest.mark.parametrize("p", [0, 1])
+def test_peaks1024_mixed_vs_exact(ctx, oracle, pc, mode, p):
+    ex = Cached("peaks1024_exact_p%d" % p)
+    same = Cached("peaks1024_same_%s_p%d" % (pc, p))
+    d_orc = same.dist(ex)
+    psi, mask = inputs("peaks1024")
+    res = ctx.solve(dev(psi), p=float(p), preconditioner=pc, tol=TOL, precision="mixed",
+                    dct_mode=mode, k_max=10, outer_tol=0.0)
+    d = ex.compare(host(res.phi), valid_pixels(oracle, psi, mask))
+    print("peaks1024 mixed %s/%s p=%d: max |phi - exact| %.3e, FP64 oracle at the same tolerance "
+          "%.3e; inner %d, refinements %d" % (pc, mode, p, d, d_orc, res.stats["inner_iters_total"],
+                                              res.stats["refinements"]))
+    assert res.stats["final_relres"] <= TOL
+    assert d <= max(3.0 * d_orc, TARGET_RAD)
+
+
+@pytest.mark.parametrize("mode", ["split_bf16", "fp16_scaled"])
+@pytest.mark.parametrize("p", [0, 1])
+def test_peaks1024_mixed_within_1e4_rad(ctx, oracle, mode, p):
+    """At the loosest swept inner tolerance where the FP64 oracle is within a
+    third of 1e-4 rad of the exact answer, the mixed path is within 1e-4 rad."""
+    ex = Cached("peaks1024_exact_p%d" % p)
+    sweep = [(t, Cached("peaks1024_tolerr_dct_p%d_%g" % (p, t)).diff) for t in (1e-7, 1e-8, 1e-9)]
+    tol = max(t for t, e in sweep if e <= TARGET_RAD / 3)
+    psi, mask = inputs("peaks1024")
+    res = ctx.solve(dev(psi), p=float(p), preconditioner="dct", tol=tol, precision="mixed",
+                    dct_mode=mode, k_max=10, outer_tol=0.0)
+    d = ex.compare(host(res.phi), valid_pixels(oracle, psi, mask))
+    print("peaks1024 mixed dct/%s p=%d at tol %g: max |phi - exact| %.3e (oracle sweep %s)"
+          % (mode, p, tol, d, sweep))
+    assert res.stats["final_relres"] <= tol
+    assert d <= TARGET_RAD
+
+
+# ---------------------------------------------------------------------------
+# 2048 x 2048 with a hole (split-bf16) and 4096 x 4096 ramp (scaled fp16)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("workload,mode", [("gauss2048_hole", "split_bf16"),
+                                           ("ramp4096", "fp16_scaled")])
+@pytest.mark.parametrize("k", [1, 10])
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_large_maps_vs_exact(ctx, oracle, workload, mode, k, precision):
+    ex = Cached("%s_exact_k%d" % (workload, k))
+    same = Cached("%s_same_k%d" % (workload, k))
+    d_orc = same.dist(ex)
+    psi, mask = inputs(workload)
+    res = ctx.solve(dev(psi), dev(mask, torch.float32) if mask is not None else None, p=0.0,
+                    preconditioner="dct", tol=TOL, precision=precision, dct_mode=mode, k_max=k,
+                    outer_tol=0.0)
+    valid = valid_pixels(oracle, psi, mask)
+    phi = host(res.phi)
+    d = ex.compare(phi, valid)
+    d_same = same.compare(phi, valid)
+    print("%s %s (%s) k=%d: max |phi - exact| %.3e, FP64 oracle at the same tolerance %.3e, "
+          "|phi - oracle same algorithm| %.3e; inner gpu %d oracle %d"
+          % (workload, precision, mode, k, d, d_orc, d_same, res.stats["inner_iters_total"],
+             sum(same.info["inner_iters"])))
+    assert res.stats["final_relres"] <= TOL
+    assert d <= max(3.0 * d_orc, TARGET_RAD)
+
+
+# ---------------------------------------------------------------------------
+# The 256-map batch
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("mode", ["fp16_scaled", "split_bf16"])
+def test_batch256_square_maps_vs_exact(ctx, oracle, mode):
+    maps = synth.batch_maps(256, seed=3000)
+    psis = [dev(p) for p, _ in maps]
+    phis, rc, stats = ctx.batch(psis, p=0.0, eps=0.01, preconditioner="dct", tol=TOL,
+                                precision="mixed", dct_mode=mode, k_max=10, outer_tol=0.0)
+    assert rc in (0, 1)
+    for side, k in BATCH_REPS.items():
+        ex = Cached("batch256_map%d_exact" % k)
+        same = Cached("batch256_map%d_same" % k)
+        d_orc = same.dist(ex)
+        psi = maps[k][0]
+        assert psi.shape == (side, side)
+        d = ex.compare(host(phis[k]), valid_pixels(oracle, psi, None))
+        print("batch256 %s map %d (%dx%d): max |phi - exact| %.3e, FP64 oracle at the same "
+              "tolerance %.3e; inner %d" % (mode, k, side, side, d, d_orc,
+                                             stats[k]["inner_iters_total"]))
+        assert stats[k]["final_relres"] <= TOL
+        assert d <= max(3.0 * d_orc, TARGET_RAD)
+
+
+def test_batch256_every_map_residual(ctx, oracle):
+    """One outer step of the whole batch from phi0 = 0: every map's phase
+    solves its system, Eq. (7) with A and b assembled by the oracle from its
+    own FP64 weights, to the tolerance (+2e-7 for the mixed path's FP32 weights)."""
+    maps = synth.batch_maps(256, seed=3000)
+    psis = [dev(p) for p, _ in maps]
+    phis, rc, stats = ctx.batch(psis, p=0.0, eps=0.01, preconditioner="dct", tol=TOL,
+                                precision="mixed", dct_mode="fp16_scaled", k_max=1, outer_tol=0.0)
+    worst = 0.0
+    for k, (psi, _) in enumerate(maps):
+        rel = oracle.true_relres(psi, None, np.zeros_like(psi), host(phis[k]), p=0.0, tau=0.01)
+        worst = max(worst, rel)
+        assert rel <= TOL + 2e-7, (k, psi.shape, rel)
+    print("batch256 one outer step: worst oracle-assembled relres %.3e over 256 maps" % worst)
