@@ -313,6 +313,29 @@ int lp_unwrap_autotune(lp_unwrap_ctx* ctx, int n_maps, const lpu_map* maps, doub
                        const char* cache_path, lpu_tuning* best, double* tune_ms);
 
 /* ----------------------------------------------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * preconditioner apply of lpu_precond_apply without any allocation.
+ *   s = M^{-1} r for every preconditioner except LPU_PC_DCT (whose tables
+ *   must be allocated; use lpu_precond_apply), same kernels and results as
+ *   lpu_precond_apply with the context's tile height.  U, V, r, s: M*N device
+ *   elements of the precision's type (caller-owned, as there).
+ *   Limits: M*N <= 1048576 pixels (1024 x 1024), at most 65536 stencil tiles,
+ *   N <= 4096 for the natural-order sweeps; larger inputs give
+ *   LPU_ERR_INVALID_ARG with a message.  omega: SSOR relaxation in (0, 2).
+ * Working memory is one static device array of about 20 MB per device, held
+ * until the process ends and shared by every call on that device: calls that
+ * overlap on one device (several streams or contexts) race and must be
+ * serialised by the caller.  The call only enqueues work on the context's
+ * stream (no allocation, no synchronisation, no host read-back) and returns
+ * LPU_OK; s is ready when the stream reaches that point.  Errors:
+ * LPU_ERR_INVALID_ARG, LPU_ERR_HIP (launch failure, or the array's address
+ * could not be looked up when the context was created).
+ * ------------------------------------------------------------------------- */
+int lpu_precond_apply_noalloc(lp_unwrap_ctx* ctx, int M, int N, int precision, int preconditioner,
+                              double omega, const void* U, const void* V, const void* r, void* s);
+
+/* ----------------------------------------------------------------------------
  * Testing hook for the failure path of Algorithm 1's inner loop: from the
  * next solve on, the step length of PCG iteration `iteration` (1-based) of
  * every inner solve is treated as a breakdown (as if d^T A d <= 0), so the

@@ -70,7 +70,7 @@ EXPORTED = ["lpu_default_options", "lp_unwrap_create", "lp_unwrap_destroy", "lp_
             "lpu_wrapped_differences", "lpu_weights", "lpu_apply_A", "lpu_rhs",
             "lpu_precond_apply", "lpu_ilu_pivots", "lpu_kernel_timing", "lpu_kernel_timing_get",
             "lpu_default_tuning", "lp_unwrap_set_tuning", "lp_unwrap_get_tuning",
-            "lp_unwrap_autotune", "lpu_debug_force_breakdown"]
+            "lp_unwrap_autotune", "lpu_debug_force_breakdown", "lpu_precond_apply_noalloc"]
 
 # kernel classes of the instrumentation (lpu_kernel_class)
 KERNEL_CLASSES = {"spmv": 0, "update": 1, "confirm": 2, "init": 3, "dct": 4, "sweep": 5,
@@ -127,6 +127,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                        ctypes.POINTER(LpuOptions), ip, ctypes.c_char_p,
                                        ctypes.POINTER(LpuTuning), ctypes.POINTER(dp)]
     lib.lp_unwrap_autotune.restype = ip
+    lib.lpu_precond_apply_noalloc.argtypes = [vp, ip, ip, ip, ip, dp, vp, vp, vp, vp]
+    lib.lpu_precond_apply_noalloc.restype = ip
     lib.lpu_debug_force_breakdown.argtypes = [vp, ctypes.c_longlong]
     lib.lpu_debug_force_breakdown.restype = ip
     return lib
@@ -413,6 +415,14 @@ class Context:
         self._raise(self._lib.lpu_precond_apply(self._h, M, N, self._prec(precision), pc, dm,
                                                 float(omega), _ptr(U), _ptr(V), _ptr(r), _ptr(s)))
         return s
+
+    def precond_apply_noalloc(self, U, V, r, s, preconditioner, *, precision="fp64", omega=1.0):
+        """lpu_precond_apply_noalloc: enqueue s = M^{-1} r into the caller's s
+        (no allocation, no synchronisation); returns the status."""
+        M, N = r.shape
+        pc = PRECONDITIONERS[preconditioner] if isinstance(preconditioner, str) else preconditioner
+        return self._lib.lpu_precond_apply_noalloc(self._h, M, N, self._prec(precision), pc,
+                                                   float(omega), _ptr(U), _ptr(V), _ptr(r), _ptr(s))
 
     def ilu_pivots(self, U, V, precision="fp64"):
         M, N = U.shape

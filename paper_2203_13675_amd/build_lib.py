@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblp_unwrap.so")
 SOURCES = ["engine_kernels.hip", "engine_dct.hip", "engine_sweep.hip", "driver.hip", "dct_tables.hip", "util.hip", "capi.hip",
-           "autotune.hip"]
+           "autotune.hip", "noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

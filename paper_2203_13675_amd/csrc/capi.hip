@@ -164,6 +164,11 @@ int lp_unwrap_create(lp_unwrap_ctx** out, int device, void* stream, int max_rows
     delete ctx;
     return LPU_ERR_HIP;
   }
+  // the no-allocation entry point's scratch array, once per device
+  if (noalloc_bind(device) != LPU_OK) {
+    lp_unwrap_destroy(ctx);
+    return LPU_ERR_HIP;
+  }
   if (max_rows > 0 && max_cols > 0) {
     if ((long long)max_rows * max_cols > (1LL << 31)) {
       lp_unwrap_destroy(ctx);

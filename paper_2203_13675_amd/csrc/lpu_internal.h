@@ -148,6 +148,9 @@ int engine_solve(lp_unwrap_ctx* ctx, int n, const lpu_map* maps, double p, doubl
                  double tol, const lpu_options& o, lpu_stats* stats);
 void engine_release(lp_unwrap_ctx* ctx);
 int engine_reserve(lp_unwrap_ctx* ctx, int M, int N);
+// noalloc.hip: look up the no-allocation entry point's scratch array on `device`
+// (current); LPU_OK or LPU_ERR_HIP
+int noalloc_bind(int device);
 int step_wrapdiff(lp_unwrap_ctx* ctx, int M, int N, const double* psi, double* dx, double* dy);
 template <typename T>
 int step_weights(lp_unwrap_ctx* ctx, int M, int N, const double* phi, const double* dx,
