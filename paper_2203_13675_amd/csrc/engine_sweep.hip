@@ -6,7 +6,7 @@
 // P = D/omega), so s = M^{-1} r is
 //   forward : y_ij = (r_ij + V_{i-1,j} y_{i-1,j} + U_{i,j-1} y_{i,j-1}) / p_ij
 //   backward: z_ij = y_ij + (U_ij z_{i,j+1} + V_ij z_{i+1,j}) / p_ij,  s = c z
-// (the solves multiply by 1 / p_ij, formed while a tile's operands are staged)
+// (the solves multiply by 1 / p_ij, formed once per tile before its wavefront)
 // (c = 2 - omega for SSOR, 1 otherwise), and the ILU(0) pivots are
 //   p_ij = a_ij - U_{i,j-1}^2 / p_{i,j-1} - V_{i-1,j}^2 / p_{i-1,j}
 // (a_ij the diagonal of A; below 1e-4 a_ij the pivot falls back to a_ij; an
@@ -30,9 +30,11 @@
 
 namespace lpu {
 
-constexpr int kWT = 64;       // tile side (rows = columns = lanes of a wave)
-constexpr int kWLD = kWT + 2;  // LDS row pitch: the wavefront's column-skewed reads hit
-                               // distinct banks
+constexpr int kWWaves = 4;               // waves per tile: all stage and store, wave 0 sweeps
+constexpr int kWThreads = 64 * kWWaves;
+constexpr int kWT = 64;  // tile side (rows = columns = lanes of a wave); LDS rows are kWT
+                         // elements apart, so the wavefront's reads (row t, column k - t)
+                         // fall in distinct banks
 
 struct WArgs {
   const MapDesc* desc;
@@ -95,98 +97,181 @@ __device__ __forceinline__ double from_prev_lane(double v) {
   return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
 }
 
+// Lane `src` (wave-uniform) of v, in every lane.
+__device__ __forceinline__ float lane_value(float v, int src) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), src));
+}
+__device__ __forceinline__ double lane_value(double v, int src) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), src);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
 __device__ __forceinline__ double wf_wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
   return v;
 }
 
-// Row loads of the tile's operands: lane l reads column j0 + l of the rows, at
-// an index clamped into the map (the load always executes, so a batch of rows
-// is in flight at once) and replaced by `outside` off the map.  Reads go
-// through global-address-space pointers, so the compiler may keep them ahead
-// of the LDS stores.
 template <typename T>
 using gptr = const __attribute__((address_space(1))) T*;
+using lptr = __attribute__((address_space(3))) void*;
+
+// In-grid element (i, j) of a map, clamped into it, and whether it is inside.
+__device__ __forceinline__ size_t wf_at(int i, int j, int M, int N, bool& ok) {
+  ok = (unsigned)i < (unsigned)M && (unsigned)j < (unsigned)N;
+  return (size_t)min(max(i, 0), M - 1) * N + min(max(j, 0), N - 1);
+}
 
 template <typename T>
 __device__ __forceinline__ T wf_ld(gptr<T> a, int i, int j, int M, int N, T outside) {
-  const bool ok = (unsigned)i < (unsigned)M && (unsigned)j < (unsigned)N;
-  const int ic = min(max(i, 0), M - 1), jc = min(max(j, 0), N - 1);
-  const T v = a[(size_t)ic * N + jc];
+  bool ok;
+  const T v = a[wf_at(i, j, M, N, ok)];
   return ok ? v : outside;
 }
 
-constexpr int kWB = 16;  // rows per batch of loads
+// One 64-element vector of array a along the tile's edge, staged like the
+// tile: element t at (i0 + t * di + oi, j0 + t * dj + oj), `outside` off the
+// map.
+template <typename T>
+struct WEdge {
+  T* dst;
+  gptr<T> src;
+  int di, dj, oi, oj;
+  T outside;
+};
 
-// Stage NA arrays: dst[q][t][c] = src[q](i0 + t + di[q], j0 + c + dj[q]), 0
-// (1 for q == one) off the map, batches of kWB rows with every load of a
-// batch issued before its LDS stores.  Array q == one is stored as its
-// reciprocal (the solves multiply by 1 / p, so no division sits on the
-// wavefront's dependency chain).
-template <typename T, int NA>
-__device__ __forceinline__ void wf_stage(T (*const (&dst)[NA])[kWLD], const gptr<T> (&src)[NA],
-                                         const int (&di)[NA], const int (&dj)[NA], int one,
-                                         const WTile& w) {
-  const int l = threadIdx.x, j = w.j0 + l;
-  for (int t0 = 0; t0 < kWT; t0 += kWB) {
-    T v[NA][kWB];
+// Stage NA arrays of the tile (dst[q][t][c] = src[q](i0 + t, j0 + c)) and NE
+// edge vectors straight from memory into LDS: one 4-byte LDS-direct load per
+// lane (a row of 64 floats, or half a row of doubles, per instruction), every
+// load issued before one wait, no registers held.  Lanes whose element lies
+// off the map read a clamped in-map element instead, and those entries are
+// then overwritten with 0 (1 for array q == one) or the edge's `outside`.
+template <typename T, int NA, int NE>
+__device__ __forceinline__ void wf_stage(T (*const (&dst)[NA])[kWT], const gptr<T> (&src)[NA],
+                                         int one, const WEdge<T> (&edge)[NE], const WTile& w) {
+  constexpr int kParts = sizeof(T) / 4;  // instructions per row
+  // one wave can keep at most 63 loads in flight, so every wave of the block
+  // takes its share of the rows (wave wv: rows wv, wv + kWWaves, ...)
+  const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  using gbyte = const __attribute__((address_space(1))) unsigned char*;
 #pragma unroll
-    for (int q = 0; q < NA; ++q)
+  for (int e = 0; e < NE; ++e) {
+    if (e % kWWaves != wv) continue;
 #pragma unroll
-      for (int u = 0; u < kWB; ++u) {
-        const int i = w.i0 + t0 + u;
-        // off the map for the tile's own pixel, or a neighbour outside it
-        const bool own = i < w.M && j < w.N;
-        const T x = wf_ld<T>(src[q], i + di[q], j + dj[q], w.M, w.N, T(0));
-        v[q][u] = own ? x : (q == one ? T(1) : T(0));
+    for (int h = 0; h < kParts; ++h) {
+      const int dw = h * 64 + l, t = dw / kParts, part = dw % kParts;
+      bool ok;
+      const size_t at = wf_at(w.i0 + t * edge[e].di + edge[e].oi, w.j0 + t * edge[e].dj + edge[e].oj,
+                              w.M, w.N, ok);
+      __builtin_amdgcn_global_load_lds((gbyte)edge[e].src + at * sizeof(T) + part * 4,
+                                       (lptr)((unsigned char*)edge[e].dst + h * 256), 4, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NA; ++q) {
+    for (int t = wv; t < kWT; t += kWWaves) {
+#pragma unroll
+      for (int h = 0; h < kParts; ++h) {
+        // dword h * 64 + l of row t's kWT elements
+        const int dw = h * 64 + l, c = dw / kParts, part = dw % kParts;
+        bool ok;
+        const size_t at = wf_at(w.i0 + t, w.j0 + c, w.M, w.N, ok);
+        __builtin_amdgcn_global_load_lds((gbyte)src[q] + at * sizeof(T) + part * 4,
+                                         (lptr)((unsigned char*)&dst[q][t][0] + h * 256), 4, 0, 0);
       }
+    }
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
 #pragma unroll
-    for (int q = 0; q < NA; ++q)
+  for (int e = 0; e < NE; ++e) {
+    if (e % kWWaves != wv) continue;
+    bool ok;
+    (void)wf_at(w.i0 + l * edge[e].di + edge[e].oi, w.j0 + l * edge[e].dj + edge[e].oj, w.M, w.N, ok);
+    if (!ok) edge[e].dst[l] = edge[e].outside;
+  }
+  if (w.i0 + kWT > w.M || w.j0 + kWT > w.N) {
+    const int j = w.j0 + l;
+    for (int t = wv; t < kWT; t += kWWaves) {
+      if (w.i0 + t < w.M && j < w.N) continue;
 #pragma unroll
-      for (int u = 0; u < kWB; ++u) dst[q][t0 + u][l] = q == one ? T(1) / v[q][u] : v[q][u];
+      for (int q = 0; q < NA; ++q) dst[q][t][l] = q == one ? T(1) : T(0);
+    }
+  }
+  __syncthreads();
+}
+
+constexpr int kWR = 4;  // steps between reading a column's operands and using them
+constexpr int kWSteps = (2 * kWT - 1 + kWR - 1) / kWR * kWR;  // wavefront steps, rounded up
+
+// Pivots of the staged tile replaced by their reciprocals (lane l: column l),
+// so the solves multiply and no division sits on the wavefront's chain.
+template <typename T>
+__device__ __forceinline__ void wf_reciprocal(T (*Pv)[kWT]) {
+  const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll 4
+  for (int t = wv; t < kWT; t += kWWaves) Pv[t][l] = T(1) / Pv[t][l];
+  __syncthreads();
+}
+
+// Rows of the tile back to memory, every wave taking its share.
+template <typename T>
+__device__ __forceinline__ void wf_store(T* out, const T (*src)[kWT], const WTile& w) {
+  const int l = threadIdx.x & 63, wv = threadIdx.x >> 6, j = w.j0 + l;
+  for (int t = wv; t < kWT; t += kWWaves) {
+    const int i = w.i0 + t;
+    if (i < w.M && j < w.N) out[(size_t)i * w.N + j] = src[t][l];
   }
 }
 
 // ---------------------------------------------------------------------------
-// ILU(0) pivots, one anti-diagonal of tiles
+// ILU(0) pivots, one anti-diagonal of tiles.  Lane l walks row l; the west
+// coupling U(i, j-1) is the U it read one step earlier, the north coupling
+// V(i-1, j) and pivot come from lane l-1's previous step.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void __launch_bounds__(kWT) k_wf_pivots(WArgs a) {
-  __shared__ T Ue[kWT][kWLD], Uw[kWT][kWLD], Vn[kWT][kWLD], Vs[kWT][kWLD];
-  __shared__ T left[kWT], top[kWT];
+__global__ void __launch_bounds__(kWThreads) k_wf_pivots(WArgs a) {
+  __shared__ T Us[kWT][kWT], Vs[kWT][kWT];
+  __shared__ T left[kWT], top[kWT], ul[kWT], vt[kWT];
   WTile w;
   if (!wf_tile<false>(a, w)) return;
   const gptr<T> U = (gptr<T>)(reinterpret_cast<const T*>(a.U) + w.off);
   const gptr<T> V = (gptr<T>)(reinterpret_cast<const T*>(a.V) + w.off);
   T* piv = reinterpret_cast<T*>(const_cast<void*>(a.piv)) + w.off;
-  const int N = w.N, l = threadIdx.x;
+  const int l = threadIdx.x & 63;
   {
-    T (*const dst[4])[kWLD] = {Ue, Uw, Vn, Vs};
-    const gptr<T> src[4] = {U, U, V, V};
-    const int di[4] = {0, 0, -1, 0}, dj[4] = {0, -1, 0, 0};
-    wf_stage<T, 4>(dst, src, di, dj, -1, w);
+    T (*const dst[2])[kWT] = {Us, Vs};
+    const gptr<T> src[2] = {U, V};
+    const WEdge<T> edge[4] = {{left, (gptr<T>)piv, 1, 0, 0, -1, T(1)},
+                              {top, (gptr<T>)piv, 0, 1, -1, 0, T(1)},
+                              {ul, U, 1, 0, 0, -1, T(0)},
+                              {vt, V, 0, 1, -1, 0, T(0)}};
+    wf_stage<T, 2, 4>(dst, src, -1, edge, w);
   }
-  {
-    const int i = w.i0 + l, j = w.j0 + l;
-    left[l] = (w.j0 > 0 && i < w.M) ? piv[(size_t)i * N + w.j0 - 1] : T(1);
-    top[l] = (w.i0 > 0 && j < N) ? piv[(size_t)(w.i0 - 1) * N + j] : T(1);
-  }
-  __syncthreads();
-  // lane l owns tile row l; at step k it computes column k - l (the pivot
-  // overwrites Ue there, whose value it has read)
-  T pw = left[l], pn = T(1);
-  T nu = T(0), nw = T(0), nn = T(0), ns = T(0);
-  if (l == 0) nu = Ue[0][0], nw = Uw[0][0], nn = Vn[0][0], ns = Vs[0][0];
+  // wave 0, lane l owns tile row l; at step k it computes column k - l (the
+  // pivot overwrites Us there, whose value it has read)
+  // Row 0's north neighbours (the tile above) are held one per lane and
+  // broadcast by lane index, so no LDS read sits on the chain.
+  if (threadIdx.x < 64) {
+  const T top_l = top[l], vt_l = vt[l];
+  T pw = left[l], pn = T(1), vn_own = T(0), uwest = ul[l];
+  T nu = T(0), nv = T(0);
+  if (l == 0) nu = Us[0][0], nv = Vs[0][0];
   for (int k = 0; k < 2 * kWT - 1; ++k) {
     const int c = k - l;
-    const T ue = nu, uw = nw, vn = nn, vs = ns;
-    const int cn = c + 1;
-    if (cn >= 0 && cn < kWT) nu = Ue[l][cn], nw = Uw[l][cn], nn = Vn[l][cn], ns = Vs[l][cn];
-    const T from_above = from_prev_lane(pn);
+    const T ue = nu, vs = nv;
+    const int cn = min(max(c + 1, 0), kWT - 1);
+    nu = Us[l][cn], nv = Vs[l][cn];
+    const T p_above = from_prev_lane(pn);
+    const T v_above = from_prev_lane(vn_own);
+    const int k0 = min(k, kWT - 1);
+    const T top_k = lane_value(top_l, k0), vt_k = lane_value(vt_l, k0);
     if (c >= 0 && c < kWT) {
+      const T uw = uwest, vn = l == 0 ? vt_k : v_above;
+      const T pup = l == 0 ? top_k : p_above;
       const T av = uw + ue + vn + vs;
-      const T pup = l == 0 ? top[c] : from_above;
       T pv;
       if (av == T(0)) {
         pv = T(1);
@@ -197,23 +282,16 @@ __global__ void __launch_bounds__(kWT) k_wf_pivots(WArgs a) {
         if (v < (T)kPivotFloor * av) v = av;
         pv = v;
       }
-      Ue[l][c] = pv;
+      Us[l][c] = pv;
       pw = pv;
       pn = pv;
+      vn_own = vs;
+      uwest = ue;
     }
+  }
   }
   __syncthreads();
-  const int j = w.j0 + l;
-  for (int t0 = 0; t0 < kWT; t0 += kWB) {
-    T v[kWB];
-#pragma unroll
-    for (int u = 0; u < kWB; ++u) v[u] = Ue[t0 + u][l];
-#pragma unroll
-    for (int u = 0; u < kWB; ++u) {
-      const int i = w.i0 + t0 + u;
-      if (i < w.M && j < N) piv[(size_t)i * N + j] = v[u];
-    }
-  }
+  wf_store<T>(piv, Us, w);
 }
 
 // SSOR "pivots" D / omega are pointwise: every active map, grid-stride.
@@ -238,9 +316,9 @@ __global__ void __launch_bounds__(256) k_wf_ssor_diag(WArgs a) {
 // Forward solve (P + L) y = r, one anti-diagonal of tiles
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void __launch_bounds__(kWT) k_wf_forward(WArgs a) {
-  __shared__ T Ry[kWT][kWLD], Pv[kWT][kWLD], Uw[kWT][kWLD], Vn[kWT][kWLD];
-  __shared__ T left[kWT], top[kWT];
+__global__ void __launch_bounds__(kWThreads) k_wf_forward(WArgs a) {
+  __shared__ T Ry[kWT][kWT], Pv[kWT][kWT], Us[kWT][kWT], Vs[kWT][kWT];
+  __shared__ T left[kWT], top[kWT], ul[kWT], vt[kWT];
   WTile w;
   if (!wf_tile<false>(a, w)) return;
   const gptr<T> U = (gptr<T>)(reinterpret_cast<const T*>(a.U) + w.off);
@@ -248,48 +326,57 @@ __global__ void __launch_bounds__(kWT) k_wf_forward(WArgs a) {
   const gptr<T> piv = (gptr<T>)(reinterpret_cast<const T*>(a.piv) + w.off);
   const gptr<T> r = (gptr<T>)(reinterpret_cast<const T*>(a.r) + w.off);
   T* y = reinterpret_cast<T*>(a.y) + w.off;
-  const int N = w.N, l = threadIdx.x;
+  const int l = threadIdx.x & 63;
   {
-    const int i = w.i0 + l, j = w.j0 + l;
-    left[l] = (w.j0 > 0 && i < w.M) ? y[(size_t)i * N + w.j0 - 1] : T(0);
-    top[l] = (w.i0 > 0 && j < N) ? y[(size_t)(w.i0 - 1) * N + j] : T(0);
-  }
-  {
-    T (*const dst[4])[kWLD] = {Ry, Pv, Uw, Vn};
+    T (*const dst[4])[kWT] = {Ry, Pv, Us, Vs};
     const gptr<T> src[4] = {r, piv, U, V};
-    const int di[4] = {0, 0, 0, -1}, dj[4] = {0, 0, -1, 0};
-    wf_stage<T, 4>(dst, src, di, dj, 1, w);
+    const WEdge<T> edge[4] = {{left, (gptr<T>)y, 1, 0, 0, -1, T(0)},
+                              {top, (gptr<T>)y, 0, 1, -1, 0, T(0)},
+                              {ul, U, 1, 0, 0, -1, T(0)},
+                              {vt, V, 0, 1, -1, 0, T(0)}};
+    wf_stage<T, 4, 4>(dst, src, 1, edge, w);
   }
-  __syncthreads();
-  T yw = left[l], yn = T(0);
-  T nr = T(0), np = T(1), nu = T(0), nv = T(0);
-  if (l == 0) nr = Ry[0][0], np = Pv[0][0], nu = Uw[0][0], nv = Vn[0][0];
-  for (int k = 0; k < 2 * kWT - 1; ++k) {
-    const int c = k - l;
-    const T cr = nr, cp = np, cu = nu, cv = nv;
-    const int cn = c + 1;
-    if (cn >= 0 && cn < kWT) nr = Ry[l][cn], np = Pv[l][cn], nu = Uw[l][cn], nv = Vn[l][cn];
-    const T from_above = from_prev_lane(yn);
-    if (c >= 0 && c < kWT) {
-      const T yup = l == 0 ? top[c] : from_above;
-      const T v = (cr + cv * yup + cu * yw) * cp;  // cp = 1 / p
-      Ry[l][c] = v;
-      yw = v;
-      yn = v;
+  wf_reciprocal<T>(Pv);
+  // The operands of column c + kWR are read kWR steps ahead into a ring of
+  // registers (at a column clamped into the tile: a step with no column of
+  // this lane ignores them), so the recurrence never waits for LDS.  Wave 0
+  // runs it, lane l on tile row l.
+  if (threadIdx.x < 64) {
+  // row 0's north neighbours, one per lane, broadcast by lane index
+  const T top_l = top[l], vt_l = vt[l];
+  T yw = left[l], yn = T(0), vn_own = T(0), uwest = ul[l];
+  T rr[kWR], pp[kWR], uu[kWR], vv[kWR];
+#pragma unroll
+  for (int u = 0; u < kWR; ++u) {
+    const int cc = min(max(u - l, 0), kWT - 1);
+    rr[u] = Ry[l][cc], pp[u] = Pv[l][cc], uu[u] = Us[l][cc], vv[u] = Vs[l][cc];
+  }
+  for (int k0 = 0; k0 < kWSteps; k0 += kWR) {
+#pragma unroll
+    for (int u = 0; u < kWR; ++u) {
+      const int k = k0 + u, c = k - l;
+      const T cr = rr[u], cinv = pp[u], cu = uu[u], cv = vv[u];
+      const int cn = min(max(c + kWR, 0), kWT - 1);
+      rr[u] = Ry[l][cn], pp[u] = Pv[l][cn], uu[u] = Us[l][cn], vv[u] = Vs[l][cn];
+      const T y_above = from_prev_lane(yn);
+      const T v_above = from_prev_lane(vn_own);
+      const int kc = min(k, kWT - 1);
+      const T top_k = lane_value(top_l, kc), vt_k = lane_value(vt_l, kc);
+      if (c >= 0 && c < kWT) {
+        const T yup = l == 0 ? top_k : y_above;
+        const T vn = l == 0 ? vt_k : v_above;
+        const T v = (cr + vn * yup + uwest * yw) * cinv;  // cinv = 1 / p
+        Ry[l][c] = v;
+        yw = v;
+        yn = v;
+        vn_own = cv;
+        uwest = cu;
+      }
     }
   }
-  __syncthreads();
-  const int j = w.j0 + l;
-  for (int t0 = 0; t0 < kWT; t0 += kWB) {
-    T v[kWB];
-#pragma unroll
-    for (int u = 0; u < kWB; ++u) v[u] = Ry[t0 + u][l];
-#pragma unroll
-    for (int u = 0; u < kWB; ++u) {
-      const int i = w.i0 + t0 + u;
-      if (i < w.M && j < N) y[(size_t)i * N + j] = v[u];
-    }
   }
+  __syncthreads();
+  wf_store<T>(y, Ry, w);
 }
 
 // ---------------------------------------------------------------------------
@@ -297,9 +384,10 @@ __global__ void __launch_bounds__(kWT) k_wf_forward(WArgs a) {
 // FP64 partial of r^T s; one anti-diagonal of tiles from the bottom-right
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void __launch_bounds__(kWT) k_wf_backward(WArgs a) {
-  __shared__ T Yz[kWT][kWLD], Pv[kWT][kWLD], Ue[kWT][kWLD], Vs[kWT][kWLD];
+__global__ void __launch_bounds__(kWThreads) k_wf_backward(WArgs a) {
+  __shared__ T Yz[kWT][kWT], Pv[kWT][kWT], Ue[kWT][kWT], Vs[kWT][kWT];
   __shared__ T right[kWT], below[kWT];
+  __shared__ double red[kWWaves];
   WTile w;
   if (!wf_tile<true>(a, w)) return;
   const gptr<T> U = (gptr<T>)(reinterpret_cast<const T*>(a.U) + w.off);
@@ -308,65 +396,80 @@ __global__ void __launch_bounds__(kWT) k_wf_backward(WArgs a) {
   const gptr<T> r = (gptr<T>)(reinterpret_cast<const T*>(a.r) + w.off);
   T* s = reinterpret_cast<T*>(a.s) + w.off;
   T* y = reinterpret_cast<T*>(a.y) + w.off;
-  const int M = w.M, N = w.N, l = threadIdx.x;
+  const int M = w.M, N = w.N, l = threadIdx.x & 63, wv = threadIdx.x >> 6;
   {
-    const int i = w.i0 + l, j = w.j0 + l, jr = w.j0 + kWT, ib = w.i0 + kWT;
-    right[l] = (jr < N && i < M) ? y[(size_t)i * N + jr] : T(0);
-    below[l] = (ib < M && j < N) ? y[(size_t)ib * N + j] : T(0);
-  }
-  {
-    T (*const dst[4])[kWLD] = {Yz, Pv, Ue, Vs};
+    T (*const dst[4])[kWT] = {Yz, Pv, Ue, Vs};
     const gptr<T> src[4] = {(gptr<T>)y, piv, U, V};
-    const int di[4] = {0, 0, 0, 0}, dj[4] = {0, 0, 0, 0};
-    wf_stage<T, 4>(dst, src, di, dj, 1, w);
+    const WEdge<T> edge[2] = {{right, (gptr<T>)y, 1, 0, 0, kWT, T(0)},
+                              {below, (gptr<T>)y, 0, 1, kWT, 0, T(0)}};
+    wf_stage<T, 4, 2>(dst, src, 1, edge, w);
   }
-  __syncthreads();
-  // lane l owns tile row 63 - l; at step k it computes column 63 - (k - l)
+  wf_reciprocal<T>(Pv);
+  // wave 0, lane l owns tile row 63 - l; at step k it computes column
+  // 63 - (k - l); operands read kWR steps ahead as in the forward solve
+  if (threadIdx.x < 64) {
   const int row = kWT - 1 - l;
+  const T below_l = below[l];  // row 63's south neighbours, broadcast by lane index
   T ze = right[row], zs = T(0);
-  T ny = T(0), np = T(1), nu = T(0), nv = T(0);
-  if (l == 0) ny = Yz[row][kWT - 1], np = Pv[row][kWT - 1], nu = Ue[row][kWT - 1],
-              nv = Vs[row][kWT - 1];
-  for (int k = 0; k < 2 * kWT - 1; ++k) {
-    const int c = kWT - 1 - (k - l);
-    const T cy = ny, cp = np, cu = nu, cv = nv;
-    const int cn = c - 1;
-    if (k + 1 - l >= 0 && cn >= 0 && cn < kWT)
-      ny = Yz[row][cn], np = Pv[row][cn], nu = Ue[row][cn], nv = Vs[row][cn];
-    const T from_below = from_prev_lane(zs);
-    if (k - l >= 0 && c >= 0) {
-      const T zdown = l == 0 ? below[c] : from_below;
-      const T v = cy + (cu * ze + cv * zdown) * cp;  // cp = 1 / p
-      Yz[row][c] = v;
-      ze = v;
-      zs = v;
-    }
+  T yy[kWR], pp[kWR], uu[kWR], vv[kWR];
+#pragma unroll
+  for (int u = 0; u < kWR; ++u) {
+    const int cc = min(max(kWT - 1 - (u - l), 0), kWT - 1);
+    yy[u] = Yz[row][cc], pp[u] = Pv[row][cc], uu[u] = Ue[row][cc], vv[u] = Vs[row][cc];
   }
-  __syncthreads();
-  const T scale = a.ssor ? (T)(2.0 - a.omega) : T(1);
-  const int j = w.j0 + l;
-  double part = 0.0;
-  for (int t0 = 0; t0 < kWT; t0 += kWB) {
-    T z[kWB], rv[kWB];
+  for (int k0 = 0; k0 < kWSteps; k0 += kWR) {
 #pragma unroll
-    for (int u = 0; u < kWB; ++u) {
-      z[u] = Yz[t0 + u][l];
-      rv[u] = wf_ld<T>(r, w.i0 + t0 + u, j, M, N, T(0));
-    }
-#pragma unroll
-    for (int u = 0; u < kWB; ++u) {
-      const int i = w.i0 + t0 + u;
-      if (i < M && j < N) {
-        const size_t p = (size_t)i * N + j;
-        const T sv = scale * z[u];
-        y[p] = z[u];
-        s[p] = sv;
-        part += (double)rv[u] * (double)sv;
+    for (int u = 0; u < kWR; ++u) {
+      const int k = k0 + u, c = kWT - 1 - (k - l);
+      const T cy = yy[u], cinv = pp[u], cu = uu[u], cv = vv[u];
+      const int cn = min(max(c - kWR, 0), kWT - 1);
+      yy[u] = Yz[row][cn], pp[u] = Pv[row][cn], uu[u] = Ue[row][cn], vv[u] = Vs[row][cn];
+      const T from_below = from_prev_lane(zs);
+      const T below_k = lane_value(below_l, max(kWT - 1 - k, 0));
+      if (c >= 0 && c < kWT) {
+        const T zdown = l == 0 ? below_k : from_below;
+        const T v = cy + (cu * ze + cv * zdown) * cinv;  // cinv = 1 / p
+        Yz[row][c] = v;
+        ze = v;
+        zs = v;
       }
     }
   }
+  }
+  __syncthreads();
+  // z back to y, s = c z, and the tile's partial of r^T s (wave wv: rows wv,
+  // wv + kWWaves, ...; the waves' sums added in a fixed order)
+  const T scale = a.ssor ? (T)(2.0 - a.omega) : T(1);
+  const int j = w.j0 + l;
+  double part = 0.0;
+  constexpr int kRows = kWT / kWWaves;
+  T z[kRows], rv[kRows];
+#pragma unroll
+  for (int u = 0; u < kRows; ++u) {
+    const int t = wv + u * kWWaves;
+    z[u] = Yz[t][l];
+    rv[u] = wf_ld<T>(r, w.i0 + t, j, M, N, T(0));
+  }
+#pragma unroll
+  for (int u = 0; u < kRows; ++u) {
+    const int i = w.i0 + wv + u * kWWaves;
+    if (i < M && j < N) {
+      const size_t p = (size_t)i * N + j;
+      const T sv = scale * z[u];
+      y[p] = z[u];
+      s[p] = sv;
+      part += (double)rv[u] * (double)sv;
+    }
+  }
   part = wf_wave_sum(part);
-  if (l == 0) store_partial(a.P + 1 * a.pstride + a.desc[w.m].dtile0 + w.local, part);
+  if (l == 0) red[wv] = part;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double tot = 0.0;
+#pragma unroll
+    for (int k = 0; k < kWWaves; ++k) tot += red[k];
+    store_partial(a.P + 1 * a.pstride + a.desc[w.m].dtile0 + w.local, tot);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -406,7 +509,7 @@ void e_pivots(hipStream_t st, const Engine& e, int nmaps, bool ssor, double omeg
   }
   for (int d = 0; d < e.wf_diags; ++d) {
     a.diag = d;
-    hipLaunchKernelGGL(k_wf_pivots<T>, dim3(std::max(1, e.wf_len), nm), dim3(kWT), 0, st, a);
+    hipLaunchKernelGGL(k_wf_pivots<T>, dim3(std::max(1, e.wf_len), nm), dim3(kWThreads), 0, st, a);
   }
 }
 
@@ -417,11 +520,11 @@ void e_sweep(hipStream_t st, const Engine& e, int nmaps, int expect, bool ssor, 
   const dim3 g(std::max(1, e.wf_len), std::max(1, nmaps));
   for (int d = 0; d < e.wf_diags; ++d) {
     a.diag = d;
-    hipLaunchKernelGGL(k_wf_forward<T>, g, dim3(kWT), 0, st, a);
+    hipLaunchKernelGGL(k_wf_forward<T>, g, dim3(kWThreads), 0, st, a);
   }
   for (int d = 0; d < e.wf_diags; ++d) {
     a.diag = d;
-    hipLaunchKernelGGL(k_wf_backward<T>, g, dim3(kWT), 0, st, a);
+    hipLaunchKernelGGL(k_wf_backward<T>, g, dim3(kWThreads), 0, st, a);
   }
 }
 
