@@ -262,7 +262,7 @@ __global__ void __launch_bounds__(kWThreads) k_wf_pivots(WArgs a) {
   for (int k = 0; k < 2 * kWT - 1; ++k) {
     const int c = k - l;
     const T ue = nu, vs = nv;
-    const int cn = min(max(c + 1, 0), kWT - 1);
+    const int cn = (c + 1) & (kWT - 1);  // wrapped for idle steps, as in the forward solve
     nu = Us[l][cn], nv = Vs[l][cn];
     const T p_above = from_prev_lane(pn);
     const T v_above = from_prev_lane(vn_own);
@@ -338,8 +338,11 @@ __global__ void __launch_bounds__(kWThreads) k_wf_forward(WArgs a) {
   }
   wf_reciprocal<T>(Pv);
   // The operands of column c + kWR are read kWR steps ahead into a ring of
-  // registers (at a column clamped into the tile: a step with no column of
-  // this lane ignores them), so the recurrence never waits for LDS.  Wave 0
+  // registers, so the recurrence never waits for LDS.  A lane with no column
+  // at a step reads column c mod 64 of its row and ignores the value: a
+  // wrapped column keeps the wave's reads in distinct banks (lane l reads
+  // word 63 l + const of the tile), where a clamped one would put every such
+  // lane on one column, a single bank.  Wave 0
   // runs it, lane l on tile row l.
   if (threadIdx.x < 64) {
   // row 0's north neighbours, one per lane, broadcast by lane index
@@ -348,7 +351,7 @@ __global__ void __launch_bounds__(kWThreads) k_wf_forward(WArgs a) {
   T rr[kWR], pp[kWR], uu[kWR], vv[kWR];
 #pragma unroll
   for (int u = 0; u < kWR; ++u) {
-    const int cc = min(max(u - l, 0), kWT - 1);
+    const int cc = (u - l) & (kWT - 1);
     rr[u] = Ry[l][cc], pp[u] = Pv[l][cc], uu[u] = Us[l][cc], vv[u] = Vs[l][cc];
   }
   for (int k0 = 0; k0 < kWSteps; k0 += kWR) {
@@ -356,7 +359,7 @@ __global__ void __launch_bounds__(kWThreads) k_wf_forward(WArgs a) {
     for (int u = 0; u < kWR; ++u) {
       const int k = k0 + u, c = k - l;
       const T cr = rr[u], cinv = pp[u], cu = uu[u], cv = vv[u];
-      const int cn = min(max(c + kWR, 0), kWT - 1);
+      const int cn = (c + kWR) & (kWT - 1);
       rr[u] = Ry[l][cn], pp[u] = Pv[l][cn], uu[u] = Us[l][cn], vv[u] = Vs[l][cn];
       const T y_above = from_prev_lane(yn);
       const T v_above = from_prev_lane(vn_own);
@@ -414,7 +417,7 @@ __global__ void __launch_bounds__(kWThreads) k_wf_backward(WArgs a) {
   T yy[kWR], pp[kWR], uu[kWR], vv[kWR];
 #pragma unroll
   for (int u = 0; u < kWR; ++u) {
-    const int cc = min(max(kWT - 1 - (u - l), 0), kWT - 1);
+    const int cc = (kWT - 1 - (u - l)) & (kWT - 1);  // wrapped as in the forward solve
     yy[u] = Yz[row][cc], pp[u] = Pv[row][cc], uu[u] = Ue[row][cc], vv[u] = Vs[row][cc];
   }
   for (int k0 = 0; k0 < kWSteps; k0 += kWR) {
@@ -422,7 +425,7 @@ __global__ void __launch_bounds__(kWThreads) k_wf_backward(WArgs a) {
     for (int u = 0; u < kWR; ++u) {
       const int k = k0 + u, c = kWT - 1 - (k - l);
       const T cy = yy[u], cinv = pp[u], cu = uu[u], cv = vv[u];
-      const int cn = min(max(c - kWR, 0), kWT - 1);
+      const int cn = (c - kWR) & (kWT - 1);
       yy[u] = Yz[row][cn], pp[u] = Pv[row][cn], uu[u] = Ue[row][cn], vv[u] = Vs[row][cn];
       const T from_below = from_prev_lane(zs);
       const T below_k = lane_value(below_l, max(kWT - 1 - k, 0));
