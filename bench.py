@@ -233,6 +233,24 @@ def main():
     }
     if tune:
         out["autotune"] = tune
+    # How full the PCG launches can be.  Every launch of an iteration covers
+    # the maps still iterating; the batch needs at least as many iteration
+    # launches as its slowest map has iterations, however the maps are
+    # scheduled, so sum(px * iters) / (max iters * total px) bounds the mean
+    # fraction of the batch's pixels per launch.
+    px_m = [m * n for m, n in shapes]
+    its = [s["inner_iters_total"] for s in stats]
+    work = sum(p * i for p, i in zip(px_m, its))
+    n_spmv = ktimes.get("spmv", {}).get("launches", 0)
+    out["iterations"] = {
+        "per_map": {"min": min(its), "median": float(np.median(its)),
+                    "p90": float(np.percentile(its, 90)), "max": max(its)},
+        "spmv_launches": n_spmv,
+        "launch_fill": work / (n_spmv * total_px) if n_spmv else None,
+        "launch_fill_bound": work / (max(its) * total_px) if max(its) > 0 else None,
+        "note": "launch_fill: pixel-iterations / (SpMV launches x batch pixels); "
+                "launch_fill_bound: the same with the slowest map's iteration count as the "
+                "launch count, the best any schedule of these maps reaches"}
 
     gpu_phis = [ph.cpu().numpy() for ph in phis]
     if a.fp64_compare and not a.profile:
