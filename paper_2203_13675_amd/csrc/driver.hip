@@ -32,8 +32,7 @@ template <typename T> void e_resid(hipStream_t, const Engine&, int, int, bool);
 template <typename T> void e_spmv(hipStream_t, const Engine&, int, int, bool);
 template <typename T> void e_update(hipStream_t, const Engine&, int, int, bool);
 template <typename T> void e_apply(hipStream_t, const Engine&, int);
-void e_finish(hipStream_t st, const Engine& e, int op, int expect, int mode, bool pointwise,
-              bool tail_single);
+void e_finish(hipStream_t st, const Engine& e, int op, int expect, int mode, bool pointwise);
 void e_dct_stage(hipStream_t st, const Engine& e, int ndtiles, int stage, int expect, int kind,
                  const void* X, void* Out, const void* rvec, int fin_mode);
 int egrid(const Engine& e, int ntiles);
@@ -74,7 +73,7 @@ static double now_ms() {
 // ---------------------------------------------------------------------------
 static void engine_free(Engine& e) {
   // counts, mact, act and dact live in one allocation that starts at counts
-  void* ptrs[] = {e.desc, e.ms, e.tile_map, e.dtile_map, e.fcnt, e.gcnt, e.eot, e.counts,
+  void* ptrs[] = {e.desc, e.ms, e.tile_map, e.dtile_map, e.fcnt, e.gcnt, e.gsum, e.eot, e.counts,
                   e.dx, e.dy, e.phi_prev, e.r64, e.U, e.V, e.aux, e.x[0], e.x[1], e.d[0],
                   e.d[1], e.r, e.s, e.q, e.b, e.t1, e.t2, e.iso, e.P};
   for (void* p : ptrs)
@@ -218,7 +217,9 @@ static int engine_setup(lp_unwrap_ctx* ctx, int n, const lpu_map* maps, int elem
     }
     A((void**)&e.fcnt, 4 * (size_t)n);
     // groups <= tiles / G + dtiles / G + 2 n for any layout within these capacities
-    A((void**)&e.gcnt, 4 * ((size_t)(tiles + dtiles) / kArriveGroup + 2 * (size_t)n + 8));
+    const long long gcap = (long long)(tiles + dtiles) / kArriveGroup + 2LL * n + 8;
+    A((void**)&e.gcnt, 4 * (size_t)gcap);
+    A((void**)&e.gsum, 8 * 2 * (size_t)gcap);
     A((void**)&e.dx, 8 * (size_t)cpx);
     A((void**)&e.dy, 8 * (size_t)cpx);
     A((void**)&e.phi_prev, 8 * (size_t)cpx);
@@ -241,6 +242,7 @@ static int engine_setup(lp_unwrap_ctx* ctx, int n, const lpu_map* maps, int elem
     e.cap_maps = n;
     e.elem = elem;
     e.pstride = pst;
+    e.gstride = gcap;
     if (hipMemset(e.iso, 0, (size_t)cpx) != hipSuccess)
       return set_error(ctx, LPU_ERR_HIP, "hipMemset");
   }
@@ -472,7 +474,7 @@ struct Pcg {
 
   void fin(hipStream_t st, int op, int expect, int mode = kFinishNone) {
     // the preconditioner partials of r^T s: one per DCT or sweep tile
-    e_finish(st, ctx->eng, op, expect, mode, pointwise(), false);
+    e_finish(st, ctx->eng, op, expect, mode, pointwise());
   }
 
   // One PCG iteration for every running map of the active set (Algorithm 1's
@@ -786,7 +788,7 @@ static int run_maps(lp_unwrap_ctx* ctx, int n, const lpu_map* maps, double p, do
       e_pass<T>(st, e, nt, kPassPhiSet);
     } else {
       e_rhs<T>(st, e, nt, 1);
-      e_finish(st, e, kFinSum2H, -1, kFinishNone, true, true);
+      e_finish(st, e, kFinSum2H, -1, kFinishNone, true);
       if ((rc = read_states(ctx))) return rc;
       setup_ms += now_ms() - ts;
       std::vector<double> rr(n, 0.0), bb(n, 0.0);
@@ -821,7 +823,7 @@ static int run_maps(lp_unwrap_ctx* ctx, int n, const lpu_map* maps, double p, do
         if ((rc = engine_activate(ctx, ref, &nt, &nd))) return rc;
         e_pass<T>(st, e, nt, kPassPhiAdd);
         e_rhs<T>(st, e, nt, 1);
-        e_finish(st, e, kFinSum2H, -1, kFinishNone, true, true);
+        e_finish(st, e, kFinSum2H, -1, kFinishNone, true);
         if ((rc = read_states(ctx))) return rc;
         for (int m : ref) {
           if (finished[m]) continue;
@@ -840,7 +842,7 @@ static int run_maps(lp_unwrap_ctx* ctx, int n, const lpu_map* maps, double p, do
     if (act2.empty()) break;
     if ((rc = engine_activate(ctx, act2, &nt, &nd))) return rc;
     e_pass<T>(st, e, nt, kPassDiffNorms);
-    e_finish(st, e, kFinSum2H, -1, kFinishNone, true, true);
+    e_finish(st, e, kFinSum2H, -1, kFinishNone, true);
     if ((rc = read_states(ctx))) return rc;
     for (int m : act2) {
       outer[m] = k + 1;
@@ -856,7 +858,7 @@ static int run_maps(lp_unwrap_ctx* ctx, int n, const lpu_map* maps, double p, do
   if (!done_any.empty()) {
     if ((rc = engine_activate(ctx, done_any, &nt, &nd))) return rc;
     e_rhs<T>(st, e, nt, 2);
-    e_finish(st, e, kFinSum2H, -1, kFinishNone, true, true);
+    e_finish(st, e, kFinSum2H, -1, kFinishNone, true);
     if ((rc = read_states(ctx))) return rc;
     for (int m : done_any)
       relres[m] = e.hms[m].bb > 0 ? std::sqrt(e.hms[m].rr / e.hms[m].bb) : 0.0;

@@ -7,9 +7,10 @@
 // that have stopped cost nothing once the host compacts the list.
 //
 // Reductions: each tile writes its FP64 partial sums to its own slot; a
-// finisher kernel (one block per map) sums the map's slots in a fixed order
-// and advances that map's PCG state.  No atomics and no grid-wide fences, so
-// results are deterministic and nothing serialises across the chip's L2s.
+// finisher (a kernel of one block per map, or fused into the tile kernel,
+// in the block that completes the map) sums the map's slots in a fixed
+// order and advances that map's PCG state.  No grid-wide fences, so results
+// are deterministic and nothing serialises across the chip's L2s.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -123,6 +124,8 @@ struct Engine {
   int* mact = nullptr;       // active maps (sweep kernels)
   int* fcnt = nullptr;       // per-map arrival counters of the fused finishers (zero between launches)
   int* gcnt = nullptr;       // per-group arrival counters (groups of kArriveGroup tiles of one map)
+  double* gsum = nullptr;    // group sums of the fused finishers: 2 rows of gstride
+  long long gstride = 0;
   EoTile* eot = nullptr;     // even/odd DCT tile records, [parity][global DCT tile]
   int* counts = nullptr;     // [0] active tiles, [1] DCT list (even stages), [2] active
                              // maps, [3] DCT list (odd stages); kListHead ints, followed

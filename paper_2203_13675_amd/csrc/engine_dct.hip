@@ -40,6 +40,8 @@ struct DArgs {
   int trows;  // output tile rows: 64 (dense kernels) or 128 (even/odd kernels)
   int cidx;   // counts[] slot holding the length of `dact`
   int *fcnt, *gcnt;  // arrival counters of the fused finisher
+  double* gsum;      // its group sums (rows of gstride)
+  long long gstride;
   const EoTile* eot;  // even/odd tile records: [stage parity][global DCT tile]
   long long eot_cap;
   int fin_mode;  // last stage of the even/odd kernels: 0, or the FinishMode of
@@ -599,9 +601,11 @@ __global__ void __launch_bounds__(256, 2) k_e_dct_eo(DArgs a) {
       double vv[1] = {part};
       block_sum<1>(vv, red);
       if (tid == 0) store_partial(a.P + 1 * a.pstride + g, vv[0]);
-      if (a.fin_mode && last_arrival(a.fcnt, a.gcnt, tm, t_local, t_ndt, t_gbd, &fflag)) {
-        finish_map(a.desc, a.ms, a.P, a.pstride, tm, kFinTail, a.fin_mode, 0, 0, fred);
-        rearm(a.fcnt, tm);
+      if (a.fin_mode) {
+        const int sl[1] = {1};
+        fused_finish<1>(Arrival{a.fcnt, a.gcnt, a.gsum, a.gstride, a.P, a.pstride}, sl,
+                        g - t_local, t_local, t_ndt, t_gbd, a.desc, a.ms, tm, kFinTail,
+                        a.fin_mode, 0, &fflag, fred);
       }
     }
   }
@@ -703,6 +707,8 @@ void e_dct_stage(hipStream_t st, const Engine& e, int ndtiles, int stage, int ex
   DArgs a;
   a.fcnt = e.fcnt;
   a.gcnt = e.gcnt;
+  a.gsum = e.gsum;
+  a.gstride = e.gstride;
   a.eot = e.eot;
   a.eot_cap = e.cap_dtiles;
   // the finisher rides on the last stage of the even/odd kernels only

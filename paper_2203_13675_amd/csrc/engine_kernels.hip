@@ -317,10 +317,16 @@ struct EArgs {
   double *dx, *dy, *phi_prev, *r64;
   const unsigned char* iso;
   int *fcnt, *gcnt;  // arrival counters of the finisher fused into the tile kernel
+  double* gsum;      // its group sums (rows of gstride)
+  long long gstride;
   int fuse_pw;  // -1: no fused finisher; else its pointwise-preconditioner flag
   int expect;   // two-colour preconditioner: state of the maps it applies to
   int fin_mode;  // two-colour preconditioner: FinishMode of its fused finisher (0: none)
 };
+
+__device__ __forceinline__ Arrival arrival(const EArgs& A) {
+  return Arrival{A.fcnt, A.gcnt, A.gsum, A.gstride, A.P, A.pstride};
+}
 
 #define TILE_LOOP(A)                                                  \
   const int n_act_ = (A).counts[0];                                   \
@@ -733,11 +739,11 @@ __global__ void __launch_bounds__(64) k_e_spmv(EArgs A) {
         });
     sdq = wave_sum(sdq);
     if (lane_id() == 0) store_partial(A.P + 0 * A.pstride + g, sdq);
-    const MapDesc& dm = A.desc[tp.m];
-    if (A.fuse_pw >= 0 &&
-        last_arrival(A.fcnt, A.gcnt, tp.m, g - dm.tile0, dm.ntiles, dm.gb, &fflag)) {
-      finish_map(A.desc, A.ms, A.P, A.pstride, tp.m, kFinAlpha, kFinishNone, A.fuse_pw, 1, fred);
-      rearm(A.fcnt, tp.m);
+    if (A.fuse_pw >= 0) {
+      const MapDesc& dm = A.desc[tp.m];
+      const int sl[1] = {0};
+      fused_finish<1>(arrival(A), sl, dm.tile0, g - dm.tile0, dm.ntiles, dm.gb, A.desc, A.ms,
+                      tp.m, kFinAlpha, kFinishNone, A.fuse_pw, &fflag, fred);
     }
   }
 }
@@ -840,11 +846,11 @@ __global__ void __launch_bounds__(64) k_e_update(EArgs A) {
       store_partial(A.P + 0 * A.pstride + g, srr);
       store_partial(A.P + 1 * A.pstride + g, srs);
     }
-    const MapDesc& dm = A.desc[tp.m];
-    if (A.fuse_pw >= 0 &&
-        last_arrival(A.fcnt, A.gcnt, tp.m, g - dm.tile0, dm.ntiles, dm.gb, &fflag)) {
-      finish_map(A.desc, A.ms, A.P, A.pstride, tp.m, kFinUpdate, kFinishNone, A.fuse_pw, 1, fred);
-      rearm(A.fcnt, tp.m);
+    if (A.fuse_pw >= 0) {
+      const MapDesc& dm = A.desc[tp.m];
+      const int sl[2] = {0, 1};
+      fused_finish<2>(arrival(A), sl, dm.tile0, g - dm.tile0, dm.ntiles, dm.gb, A.desc, A.ms,
+                      tp.m, kFinUpdate, kFinishNone, A.fuse_pw, &fflag, fred);
     }
   }
 }
@@ -958,10 +964,11 @@ __global__ void __launch_bounds__(64) k_e_twocolor(EArgs A, T c) {
     if (PASS == 1) {
       part = wave_sum(part);
       if (lane_id() == 0) store_partial(A.P + 1 * A.pstride + g, part);
-      const MapDesc& dm = A.desc[tp.m];
-      if (A.fin_mode && last_arrival(A.fcnt, A.gcnt, tp.m, g - dm.tile0, dm.ntiles, dm.gb, &fflag)) {
-        finish_map(A.desc, A.ms, A.P, A.pstride, tp.m, kFinTailS, A.fin_mode, 0, 0, fred);
-        rearm(A.fcnt, tp.m);
+      if (A.fin_mode) {
+        const MapDesc& dm = A.desc[tp.m];
+        const int sl[1] = {1};
+        fused_finish<1>(arrival(A), sl, dm.tile0, g - dm.tile0, dm.ntiles, dm.gb, A.desc, A.ms,
+                        tp.m, kFinTailS, A.fin_mode, 0, &fflag, fred);
       }
     }
   }
@@ -990,12 +997,12 @@ __global__ void __launch_bounds__(64) k_e_apply(EArgs A) {
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_e_finish(const MapDesc* __restrict__ desc, MapState* ms,
                                                   const double* __restrict__ P, long long pstride,
-                                                  int op, int expect, int mode, int pointwise,
-                                                  int tail_single) {
+                                                  int op, int expect, int mode, int pointwise) {
   __shared__ double red[3 * 4];
   const int m = blockIdx.x;
   if (expect >= 0 && ms[m].state != expect) return;
-  finish_map(desc, ms, P, pstride, m, op, mode, pointwise, tail_single, red);
+  const FinSrc src{P, pstride, nullptr, 0};
+  finish_map<false>(desc, ms, src, m, op, mode, pointwise, red);
 }
 
 // ---------------------------------------------------------------------------
@@ -1037,6 +1044,8 @@ EArgs make_args(const Engine& e) {
   a.iso = e.iso;
   a.fcnt = e.fcnt;
   a.gcnt = e.gcnt;
+  a.gsum = e.gsum;
+  a.gstride = e.gstride;
   a.fuse_pw = -1;
   a.expect = kRun;
   a.fin_mode = 0;
@@ -1173,10 +1182,9 @@ void e_apply(hipStream_t st, const Engine& e, int ntiles) {
   hipLaunchKernelGGL(k_e_apply<T>, dim3(egrid(e, ntiles)), dim3(64), 0, st, make_args(e));
 }
 
-void e_finish(hipStream_t st, const Engine& e, int op, int expect, int mode, bool pointwise,
-              bool tail_single) {
+void e_finish(hipStream_t st, const Engine& e, int op, int expect, int mode, bool pointwise) {
   hipLaunchKernelGGL(k_e_finish, dim3(e.n_maps), dim3(256), 0, st, e.desc, e.ms, e.P, e.pstride,
-                     op, expect, mode, pointwise ? 1 : 0, tail_single ? 1 : 0);
+                     op, expect, mode, pointwise ? 1 : 0);
 }
 
 #define LPU_INST_E(T)                                                                   \

@@ -80,15 +80,55 @@ __device__ __forceinline__ double load_partial(const double* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Where a finisher reads a map's sums: the tile partials (P, one row of
+// pstride doubles per slot), or the group sums a fused kernel published
+// (gsum, one row of gstride doubles per entry of the op's slot list).
+struct FinSrc {
+  const double* P;
+  long long pstride;
+  const double* gsum;
+  long long gstride;
+};
+
+// Association of the sums over a map's tiles.  They are fixed functions of
+// the map and the kernel (so runs are bit-reproducible and a map's result
+// does not depend on its batch-mates or on the launch shape):
+//  * flat (standalone finishers, and fused ones whose block reads every
+//    partial in one round of at most kFlatLoads loads per thread): thread t
+//    adds partials t, t + blockDim, ... in order, then a fixed tree adds the
+//    threads;
+//  * grouped (fused finishers of larger maps): the tiles in groups of
+//    kArriveGroup consecutive tiles, a group's sum a pairwise tree over its
+//    32 partials (absent tiles count as 0), formed by the block that
+//    completes the group (last_arrival); the map's sum then formed by one
+//    wave, lane k adding the sums of groups k, k + 64, ... in order, then a
+//    pairwise tree over the 64 lanes.  The map's last block reads one value
+//    per group instead of every tile's partial.
+constexpr int kFlatLoads = 8;
+static_assert(kArriveGroup == 32, "a group's sum is a tree over half a wave");
+
+__device__ __forceinline__ double tree32(double v) {  // lanes 0 and 32: the sum of their half
+#pragma unroll
+  for (int off = 16; off > 0; off >>= 1) v += __shfl_down(v, off, 32);
+  return v;
+}
+__device__ __forceinline__ double tree64(double v) {  // lane 0: the sum of the wave
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+// Flat sums of `count` tile partials from `first`, one per entry of `slots`;
+// every thread of the block takes part; the result is valid in thread 0.
+// smem: 3 * blockDim.x / 64 doubles.
 template <int NS>
-__device__ __forceinline__ void fin_sums(const double* __restrict__ P, long long pstride, int first,
-                                         int count, const int* slots, double (&out)[NS],
-                                         double* smem) {
-  // Each thread adds the partials t = tid, tid + blockDim, ... in that order;
-  // the loads of eight consecutive terms are issued together, since they go
-  // to the level the XCDs share and a chain of single loads would put their
-  // full latency on the map's finisher, often the last work of a launch.
-  constexpr int kU = 8;
+__device__ __forceinline__ void fin_sums_flat(const double* __restrict__ P, long long pstride,
+                                              int first, int count, const int (&slots)[NS],
+                                              double (&out)[NS], double* smem) {
+  // The loads of kFlatLoads consecutive terms are issued together, since
+  // they go to the level the XCDs share and a chain of single loads would put
+  // their full latency on the map's finisher, often the last work of a launch.
+  constexpr int kU = kFlatLoads;
   const int nb = blockDim.x;
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
@@ -110,36 +150,76 @@ __device__ __forceinline__ void fin_sums(const double* __restrict__ P, long long
   block_sum<NS>(out, smem);
 }
 
+// Grouped sums from the group sums of `ngrp` groups from `gbase`; wave 0
+// only (the other waves' results are zeros); the result is valid in thread 0.
+template <int NS>
+__device__ __forceinline__ void fin_sums_groups(const double* __restrict__ gsum, long long gstride,
+                                                int gbase, int ngrp, double (&out)[NS]) {
+  constexpr int kU = 4;  // few registers: the finisher is fused into tile kernels
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    const double* base = gsum + k * gstride + gbase;
+    double acc = 0.0;
+    if (threadIdx.x < 64) {
+      for (int j0 = 0; j0 < ngrp; j0 += 64 * kU) {
+        double x[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const int j = j0 + 64 * u + lane;
+          x[u] = j < ngrp ? load_partial(base + j) : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u)
+          if (j0 + 64 * u + lane < ngrp) acc += x[u];
+      }
+    }
+    out[k] = tree64(acc);
+  }
+}
+
+// GROUPS: from the group sums (a fused finisher of a large map), else flat
+template <bool GROUPS, int NS>
+__device__ __forceinline__ void fin_sums(const FinSrc& src, int first, int count, int gbase,
+                                         const int (&slots)[NS], double (&out)[NS], double* smem) {
+  if constexpr (GROUPS)
+    fin_sums_groups<NS>(src.gsum, src.gstride, gbase, (count + kArriveGroup - 1) / kArriveGroup,
+                        out);
+  else
+    fin_sums_flat<NS>(src.P, src.pstride, first, count, slots, out, smem);
+}
+
 // One map's finisher, executed by every thread of the calling block (any
-// multiple of 64 threads); smem holds 3 * blockDim.x / 64 doubles.
-__device__ inline void finish_map(const MapDesc* __restrict__ desc, MapState* ms,
-                                  const double* __restrict__ P, long long pstride, int m, int op,
-                                  int mode, int pointwise, int tail_single, double* smem) {
+// multiple of 64 threads); GROUPS: the sums from the group sums (smem
+// unused), else flat (smem: 3 * blockDim.x / 64 doubles).
+template <bool GROUPS>
+__device__ inline void finish_map(const MapDesc* __restrict__ desc, MapState* ms, const FinSrc& src,
+                                  int m, int op, int mode, int pointwise, double* smem) {
   MapState& s = ms[m];
   const MapDesc& d = desc[m];
   double v[3] = {0.0, 0.0, 0.0};
   if (op == kFinInit) {
     const int sl[3] = {0, 1, 2};
-    fin_sums<3>(P, pstride, d.tile0, d.ntiles, sl, v, smem);
+    fin_sums<GROUPS, 3>(src, d.tile0, d.ntiles, d.gb, sl, v, smem);
   } else if (op == kFinAlpha) {
     const int sl[1] = {0};
     double w[1];
-    fin_sums<1>(P, pstride, d.tile0, d.ntiles, sl, w, smem);
+    fin_sums<GROUPS, 1>(src, d.tile0, d.ntiles, d.gb, sl, w, smem);
     v[0] = w[0];
   } else if (op == kFinTail) {
     const int sl[1] = {1};
     double w[1];
-    fin_sums<1>(P, pstride, d.dtile0, tail_single ? 1 : d.ndt, sl, w, smem);
+    fin_sums<GROUPS, 1>(src, d.dtile0, d.ndt, d.gbd, sl, w, smem);
     v[0] = w[0];
   } else if (op == kFinTailS) {
     const int sl[1] = {1};
     double w[1];
-    fin_sums<1>(P, pstride, d.tile0, d.ntiles, sl, w, smem);
+    fin_sums<GROUPS, 1>(src, d.tile0, d.ntiles, d.gb, sl, w, smem);
     v[0] = w[0];
   } else {
     const int sl[2] = {0, 1};
     double w[2];
-    fin_sums<2>(P, pstride, d.tile0, d.ntiles, sl, w, smem);
+    fin_sums<GROUPS, 2>(src, d.tile0, d.ntiles, d.gb, sl, w, smem);
     v[0] = w[0];
     v[1] = w[1];
   }
@@ -205,43 +285,104 @@ __device__ inline void finish_map(const MapDesc* __restrict__ desc, MapState* ms
   }
 }
 
-// Arrival of tile `local` (of `total`) of map m, by thread 0 after it stored
-// the tile's partials with store_partial: true in the block whose tile is the
-// map's last of this launch, which then finishes the map and rearms the map
-// counter.  Tiles first count in their group of kArriveGroup (counter
-// gcnt[gbase + local / kArriveGroup]); the last of a group counts once in the
-// map's counter, so no counter takes more than a few dozen atomics (one
-// address takes them one at a time).  The partials are agent-coherent
-// stores (written through to the level the XCDs share) and thread 0 waits
-// for their completion before its agent-scope atomics; each later arrival
-// follows a returned atomic, and the finishing block reads the partials with
-// agent-coherent loads.  That orders exactly the data exchanged, without an
-// L2 write-back.
-__device__ inline bool last_arrival(int* fcnt, int* gcnt, int m, int local, int total, int gbase,
-                                    int* flag) {
-  if (threadIdx.x == 0) {
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
-    __builtin_amdgcn_s_waitcnt(0);
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
-    const int grp = local / kArriveGroup;
-    const int in_grp = min(kArriveGroup, total - grp * kArriveGroup);
-    const int ngrp = (total + kArriveGroup - 1) / kArriveGroup;
-    int* gc = gcnt + gbase + grp;
-    int last = 0;
-    if (__hip_atomic_fetch_add(gc, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == in_grp - 1) {
-      __hip_atomic_store(gc, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);  // rearm the group
-      __atomic_signal_fence(__ATOMIC_SEQ_CST);
-      last = __hip_atomic_fetch_add(fcnt + m, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
-             ngrp - 1;
-    }
-    *flag = last;
-  }
-  __syncthreads();
-  return *flag != 0;
+// Arrival of tile `local` (of `total`, from tile `first`) of map m, after
+// its thread 0 stored the tile's partials of the op's slots with
+// store_partial.  Tiles first count in their group of kArriveGroup (counter
+// gcnt[gbase + local / kArriveGroup]); the block that completes a group
+// counts once in the map's counter, so no counter takes more than a few
+// dozen atomics (one address takes them one at a time).  For a map whose
+// partials the finishing block cannot read in one round (more than
+// kFlatLoads per thread), the block that completes a group first forms the
+// group's sums and publishes them in gsum (row k for slots[k], column
+// gbase + group).  Partials and group sums are agent-coherent stores
+// (written through to the level the XCDs share) whose completion the storing
+// wave waits for before its agent-scope atomic; each later arrival follows a
+// returned atomic, and the blocks that read them use agent-coherent loads.
+// That orders exactly the data exchanged, without an L2 write-back.
+struct Arrival {
+  int* fcnt;
+  int* gcnt;
+  double* gsum;
+  long long gstride;
+  const double* P;
+  long long pstride;
+};
+
+__device__ __forceinline__ void wait_stores() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
-__device__ inline void rearm(int* cnt, int m) {
-  if (threadIdx.x == 0) __hip_atomic_store(cnt + m, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+enum ArrivalKind : int {
+  kArrNotLast = 0,  // not the map's last block
+  kArrFlat = 1,     // the map's last block: flat sums of the tile partials
+  kArrGroups = 2    // the map's last block: sums of the published group sums
+};
+
+// flag is shared memory.
+template <int NS>
+__device__ inline int last_arrival(const Arrival& a, const int (&slots)[NS], int first, int m,
+                                   int local, int total, int gbase, int* flag) {
+  static_assert(NS <= 2, "one slot per half-wave");
+  const int grp = local / kArriveGroup;
+  const int ngrp = (total + kArriveGroup - 1) / kArriveGroup;
+  const bool publish = total > kFlatLoads * (int)blockDim.x;
+  if (threadIdx.x == 0) {
+    wait_stores();
+    const int in_grp = min(kArriveGroup, total - grp * kArriveGroup);
+    int kind = kArrNotLast;
+    if (__hip_atomic_fetch_add(a.gcnt + gbase + grp, 1, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT) == in_grp - 1) {
+      __hip_atomic_store(a.gcnt + gbase + grp, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      kind = kArrGroups;  // this block completed the group
+      if (!publish)
+        kind = __hip_atomic_fetch_add(a.fcnt + m, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+                       ngrp - 1
+                   ? kArrFlat
+                   : kArrNotLast;
+    }
+    *flag = kind;
+  }
+  __syncthreads();
+  if (!publish || *flag == kArrNotLast) return *flag;  // uniform over the block
+  __syncthreads();  // every thread has read the flag
+  if (threadIdx.x < 64) {
+    // the group's sums: lanes 0-31 the first slot, lanes 32-63 the second
+    const int lane = threadIdx.x, k = lane >> 5;
+    const int t = grp * kArriveGroup + (lane & 31);
+    const double x = (k < NS && t < total)
+                         ? load_partial(a.P + slots[k < NS ? k : 0] * a.pstride + first + t)
+                         : 0.0;
+    const double v = tree32(x);
+    if ((lane & 31) == 0 && k < NS) store_partial(a.gsum + k * a.gstride + gbase + grp, v);
+    if (lane == 0) {
+      wait_stores();
+      *flag = __hip_atomic_fetch_add(a.fcnt + m, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+                      ngrp - 1
+                  ? kArrGroups
+                  : kArrNotLast;
+    }
+  }
+  __syncthreads();
+  return *flag;
+}
+
+// The finisher fused into a tile kernel: the arrival of tile `local` (of
+// `total`, from tile `first`) of map m after its partials of `slots` were
+// stored, and in the block that completes the map, the map's finisher (then
+// the map counter is rearmed).  flag and smem (3 * blockDim.x / 64 doubles)
+// are shared memory.
+template <int NS>
+__device__ inline void fused_finish(const Arrival& a, const int (&slots)[NS], int first, int local,
+                                    int total, int gbase, const MapDesc* desc, MapState* ms, int m,
+                                    int op, int mode, int pointwise, int* flag, double* smem) {
+  const int kind = last_arrival<NS>(a, slots, first, m, local, total, gbase, flag);
+  if (kind == kArrNotLast) return;
+  const FinSrc src{a.P, a.pstride, a.gsum, a.gstride};
+  if (kind == kArrFlat) finish_map<false>(desc, ms, src, m, op, mode, pointwise, smem);
+  else finish_map<true>(desc, ms, src, m, op, mode, pointwise, smem);
+  if (threadIdx.x == 0) __hip_atomic_store(a.fcnt + m, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 }  // namespace lpu
