@@ -97,6 +97,21 @@ __device__ __forceinline__ double from_prev_lane(double v) {
   return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
 }
 
+// DPP whole-wave shift with a fill: lane l receives lane l-1's v, lane 0 keeps
+// its own value of fill.
+__device__ __forceinline__ int wshr_fill(int fill, int v) {
+  return __builtin_amdgcn_update_dpp(fill, v, 0x138, 0xF, 0xF, false);
+}
+__device__ __forceinline__ float from_prev_lane(float fill, float v) {
+  return __builtin_bit_cast(float, wshr_fill(__builtin_bit_cast(int, fill), __builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ double from_prev_lane(double fill, double v) {
+  const long long f = __builtin_bit_cast(long long, fill), b = __builtin_bit_cast(long long, v);
+  const int lo = wshr_fill((int)(f & 0xffffffffLL), (int)(b & 0xffffffffLL));
+  const int hi = wshr_fill((int)(f >> 32), (int)(b >> 32));
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
 // Lane `src` (wave-uniform) of v, in every lane.
 __device__ __forceinline__ float lane_value(float v, int src) {
   return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), src));
@@ -206,13 +221,29 @@ __device__ __forceinline__ void wf_stage(T (*const (&dst)[NA])[kWT], const gptr<
 constexpr int kWR = 4;  // steps between reading a column's operands and using them
 constexpr int kWSteps = (2 * kWT - 1 + kWR - 1) / kWR * kWR;  // wavefront steps, rounded up
 
-// Pivots of the staged tile replaced by their reciprocals (lane l: column l),
-// so the solves multiply and no division sits on the wavefront's chain.
+// The staged pivots and U of the tile (two 64 x 64 arrays, pivots first, in
+// pu's space) rewritten in place as {1 / p, U} pairs, so the solves multiply
+// (no division on the wavefront's chain) and read both with one instruction.
+// Every thread reads its elements before any is written.
 template <typename T>
-__device__ __forceinline__ void wf_reciprocal(T (*Pv)[kWT]) {
+__device__ __forceinline__ void wf_pivot_pairs(T (*pu)[kWT][2]) {
+  constexpr int kPer = kWT / kWWaves;
   const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll 4
-  for (int t = wv; t < kWT; t += kWWaves) Pv[t][l] = T(1) / Pv[t][l];
+  const T* staged = &pu[0][0][0];
+  T pv[kPer], uv[kPer];
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) {
+    const int t = wv + kWWaves * i;
+    pv[i] = staged[t * kWT + l];
+    uv[i] = staged[kWT * kWT + t * kWT + l];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) {
+    const int t = wv + kWWaves * i;
+    pu[t][l][0] = T(1) / pv[i];
+    pu[t][l][1] = uv[i];
+  }
   __syncthreads();
 }
 
@@ -317,8 +348,13 @@ __global__ void __launch_bounds__(256) k_wf_ssor_diag(WArgs a) {
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(kWThreads) k_wf_forward(WArgs a) {
-  __shared__ T Ry[kWT][kWT], Pv[kWT][kWT], Us[kWT][kWT], Vs[kWT][kWT];
-  __shared__ T left[kWT], top[kWT], ul[kWT], vt[kWT];
+  // sm[0]: r, overwritten by y; sm[1]: V.  Row 0 of each holds the row
+  // above the tile (its y and V), rows 1..64 the tile, so one instruction
+  // reads a lane's operand and the value above it, and both arrays are read
+  // from one address.  pu: {1 / p, U} pairs of the tile.
+  __shared__ __attribute__((aligned(16))) T sm[2][kWT + 1][kWT];
+  __shared__ __attribute__((aligned(16))) T pu[kWT][kWT][2];
+  __shared__ T left[kWT], ul[kWT];
   WTile w;
   if (!wf_tile<false>(a, w)) return;
   const gptr<T> U = (gptr<T>)(reinterpret_cast<const T*>(a.U) + w.off);
@@ -328,58 +364,56 @@ __global__ void __launch_bounds__(kWThreads) k_wf_forward(WArgs a) {
   T* y = reinterpret_cast<T*>(a.y) + w.off;
   const int l = threadIdx.x & 63;
   {
-    T (*const dst[4])[kWT] = {Ry, Pv, Us, Vs};
+    T* const stg = &pu[0][0][0];
+    T (*const dst[4])[kWT] = {&sm[0][1], reinterpret_cast<T (*)[kWT]>(stg),
+                              reinterpret_cast<T (*)[kWT]>(stg + kWT * kWT), &sm[1][1]};
     const gptr<T> src[4] = {r, piv, U, V};
-    const WEdge<T> edge[4] = {{left, (gptr<T>)y, 1, 0, 0, -1, T(0)},
-                              {top, (gptr<T>)y, 0, 1, -1, 0, T(0)},
-                              {ul, U, 1, 0, 0, -1, T(0)},
-                              {vt, V, 0, 1, -1, 0, T(0)}};
-    wf_stage<T, 4, 4>(dst, src, 1, edge, w);
+    const WEdge<T> e[4] = {{left, (gptr<T>)y, 1, 0, 0, -1, T(0)},
+                           {&sm[0][0][0], (gptr<T>)y, 0, 1, -1, 0, T(0)},
+                           {ul, U, 1, 0, 0, -1, T(0)},
+                           {&sm[1][0][0], V, 0, 1, -1, 0, T(0)}};
+    wf_stage<T, 4, 4>(dst, src, 1, e, w);
   }
-  wf_reciprocal<T>(Pv);
-  // The operands of column c + kWR are read kWR steps ahead into a ring of
-  // registers, so the recurrence never waits for LDS.  A lane with no column
-  // at a step reads column c mod 64 of its row and ignores the value: a
-  // wrapped column keeps the wave's reads in distinct banks (lane l reads
-  // word 63 l + const of the tile), where a clamped one would put every such
-  // lane on one column, a single bank.  Wave 0
-  // runs it, lane l on tile row l.
+  wf_pivot_pairs<T>(pu);
+  // Wave 0 runs the wavefront, lane l on tile row l.  The operands of
+  // column c + kWR are read kWR steps ahead into a ring of registers (each
+  // slot refilled after its step used it), so the recurrence never waits for
+  // LDS.  A lane with no column at a step reads column c mod 64 of its row
+  // and ignores the value: a wrapped column keeps the wave's reads in
+  // distinct banks (lane l reads word 63 l + const of the tile), where a
+  // clamped one would put every such lane on one column, a single bank.  The
+  // north neighbours come from lane l - 1's previous step by a DPP shift;
+  // lane 0 keeps the values above the tile, which its reads of the row above
+  // its own fetched.
   if (threadIdx.x < 64) {
-  // row 0's north neighbours, one per lane, broadcast by lane index
-  const T top_l = top[l], vt_l = vt[l];
-  T yw = left[l], yn = T(0), vn_own = T(0), uwest = ul[l];
-  T rr[kWR], pp[kWR], uu[kWR], vv[kWR];
+  T y_own = left[l], vn_own = T(0), uwest = ul[l];
+  T ra[kWR], rr[kWR], va[kWR], vv[kWR], pp[kWR], uu[kWR];
+  auto fetch = [&](int u, int col) {
+    ra[u] = sm[0][l][col], rr[u] = sm[0][l + 1][col];
+    va[u] = sm[1][l][col], vv[u] = sm[1][l + 1][col];
+    pp[u] = pu[l][col][0], uu[u] = pu[l][col][1];
+  };
 #pragma unroll
-  for (int u = 0; u < kWR; ++u) {
-    const int cc = (u - l) & (kWT - 1);
-    rr[u] = Ry[l][cc], pp[u] = Pv[l][cc], uu[u] = Us[l][cc], vv[u] = Vs[l][cc];
-  }
+  for (int u = 0; u < kWR; ++u) fetch(u, (u - l) & (kWT - 1));
   for (int k0 = 0; k0 < kWSteps; k0 += kWR) {
 #pragma unroll
     for (int u = 0; u < kWR; ++u) {
-      const int k = k0 + u, c = k - l;
-      const T cr = rr[u], cinv = pp[u], cu = uu[u], cv = vv[u];
-      const int cn = (c + kWR) & (kWT - 1);
-      rr[u] = Ry[l][cn], pp[u] = Pv[l][cn], uu[u] = Us[l][cn], vv[u] = Vs[l][cn];
-      const T y_above = from_prev_lane(yn);
-      const T v_above = from_prev_lane(vn_own);
-      const int kc = min(k, kWT - 1);
-      const T top_k = lane_value(top_l, kc), vt_k = lane_value(vt_l, kc);
+      const int c = k0 + u - l;
+      const T yup = from_prev_lane(ra[u], y_own);  // lane 0: y of the row above, column k
+      const T vn = from_prev_lane(va[u], vn_own);
       if (c >= 0 && c < kWT) {
-        const T yup = l == 0 ? top_k : y_above;
-        const T vn = l == 0 ? vt_k : v_above;
-        const T v = (cr + vn * yup + uwest * yw) * cinv;  // cinv = 1 / p
-        Ry[l][c] = v;
-        yw = v;
-        yn = v;
-        vn_own = cv;
-        uwest = cu;
+        const T v = (rr[u] + vn * yup + uwest * y_own) * pp[u];  // pp = 1 / p
+        sm[0][l + 1][c] = v;
+        y_own = v;
+        vn_own = vv[u];
+        uwest = uu[u];
       }
+      fetch(u, (c + kWR) & (kWT - 1));
     }
   }
   }
   __syncthreads();
-  wf_store<T>(y, Ry, w);
+  wf_store<T>(y, &sm[0][1], w);
 }
 
 // ---------------------------------------------------------------------------
@@ -388,9 +422,14 @@ __global__ void __launch_bounds__(kWThreads) k_wf_forward(WArgs a) {
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(kWThreads) k_wf_backward(WArgs a) {
-  __shared__ T Yz[kWT][kWT], Pv[kWT][kWT], Ue[kWT][kWT], Vs[kWT][kWT];
-  __shared__ T right[kWT], below[kWT];
+  // sm rows 0..63: y of the tile, overwritten by z; row 64: z of the row
+  // below the tile; rows 65..128: V of the tile (so a lane's operand, the
+  // value below it and its V are read from one address).  pu: {1 / p, U}.
+  __shared__ __attribute__((aligned(16))) T sm[2 * kWT + 1][kWT];
+  __shared__ __attribute__((aligned(16))) T pu[kWT][kWT][2];
+  __shared__ T right[kWT];
   __shared__ double red[kWWaves];
+  T (*const Yz)[kWT] = sm;
   WTile w;
   if (!wf_tile<true>(a, w)) return;
   const gptr<T> U = (gptr<T>)(reinterpret_cast<const T*>(a.U) + w.off);
@@ -401,41 +440,39 @@ __global__ void __launch_bounds__(kWThreads) k_wf_backward(WArgs a) {
   T* y = reinterpret_cast<T*>(a.y) + w.off;
   const int M = w.M, N = w.N, l = threadIdx.x & 63, wv = threadIdx.x >> 6;
   {
-    T (*const dst[4])[kWT] = {Yz, Pv, Ue, Vs};
+    T* const stg = &pu[0][0][0];
+    T (*const dst[4])[kWT] = {&sm[0], reinterpret_cast<T (*)[kWT]>(stg),
+                              reinterpret_cast<T (*)[kWT]>(stg + kWT * kWT), &sm[kWT + 1]};
     const gptr<T> src[4] = {(gptr<T>)y, piv, U, V};
     const WEdge<T> edge[2] = {{right, (gptr<T>)y, 1, 0, 0, kWT, T(0)},
-                              {below, (gptr<T>)y, 0, 1, kWT, 0, T(0)}};
+                              {&sm[kWT][0], (gptr<T>)y, 0, 1, kWT, 0, T(0)}};
     wf_stage<T, 4, 2>(dst, src, 1, edge, w);
   }
-  wf_reciprocal<T>(Pv);
+  wf_pivot_pairs<T>(pu);
   // wave 0, lane l owns tile row 63 - l; at step k it computes column
-  // 63 - (k - l); operands read kWR steps ahead as in the forward solve
+  // 63 - (k - l); operands read kWR steps ahead, and lane 0's south
+  // neighbours (the row below the tile) carried as in the forward solve
   if (threadIdx.x < 64) {
   const int row = kWT - 1 - l;
-  const T below_l = below[l];  // row 63's south neighbours, broadcast by lane index
-  T ze = right[row], zs = T(0);
-  T yy[kWR], pp[kWR], uu[kWR], vv[kWR];
+  T z_own = right[row];
+  T yy[kWR], yb[kWR], vv[kWR], pp[kWR], uu[kWR];
+  auto fetch = [&](int u, int col) {
+    yy[u] = sm[row][col], yb[u] = sm[row + 1][col], vv[u] = sm[kWT + 1 + row][col];
+    pp[u] = pu[row][col][0], uu[u] = pu[row][col][1];
+  };
 #pragma unroll
-  for (int u = 0; u < kWR; ++u) {
-    const int cc = (kWT - 1 - (u - l)) & (kWT - 1);  // wrapped as in the forward solve
-    yy[u] = Yz[row][cc], pp[u] = Pv[row][cc], uu[u] = Ue[row][cc], vv[u] = Vs[row][cc];
-  }
+  for (int u = 0; u < kWR; ++u) fetch(u, (kWT - 1 - (u - l)) & (kWT - 1));  // wrapped as forward
   for (int k0 = 0; k0 < kWSteps; k0 += kWR) {
 #pragma unroll
     for (int u = 0; u < kWR; ++u) {
-      const int k = k0 + u, c = kWT - 1 - (k - l);
-      const T cy = yy[u], cinv = pp[u], cu = uu[u], cv = vv[u];
-      const int cn = (c - kWR) & (kWT - 1);
-      yy[u] = Yz[row][cn], pp[u] = Pv[row][cn], uu[u] = Ue[row][cn], vv[u] = Vs[row][cn];
-      const T from_below = from_prev_lane(zs);
-      const T below_k = lane_value(below_l, max(kWT - 1 - k, 0));
+      const int c = kWT - 1 - (k0 + u - l);
+      const T zdown = from_prev_lane(yb[u], z_own);  // lane 0: z of the row below, column 63 - k
       if (c >= 0 && c < kWT) {
-        const T zdown = l == 0 ? below_k : from_below;
-        const T v = cy + (cu * ze + cv * zdown) * cinv;  // cinv = 1 / p
+        const T v = yy[u] + (uu[u] * z_own + vv[u] * zdown) * pp[u];  // pp = 1 / p
         Yz[row][c] = v;
-        ze = v;
-        zs = v;
+        z_own = v;
       }
+      fetch(u, (c - kWR) & (kWT - 1));
     }
   }
   }
