@@ -157,12 +157,12 @@ struct WEdge {
   T outside;
 };
 
-// Stage NA arrays of the tile (dst[q][t][c] = src[q](i0 + t, j0 + c)) and NE
-// edge vectors straight from memory into LDS: one 4-byte LDS-direct load per
-// lane (a row of 64 floats, or half a row of doubles, per instruction), every
-// load issued before one wait, no registers held.  Lanes whose element lies
-// off the map read a clamped in-map element instead, and those entries are
-// then overwritten with 0 (1 for array q == one) or the edge's `outside`.
+// Stage NA arrays of the tile (dst[q][t][c] = src[q](i0 + t, j0 + c); the
+// rows of each dst contiguous) and NE edge vectors straight from memory into
+// LDS with LDS-direct loads, every load issued before one wait, no registers
+// held.  Lanes whose element lies off the map read a clamped in-map element
+// instead, and those entries are then overwritten with 0 (1 for array
+// q == one) or the edge's `outside`.
 template <typename T, int NA, int NE>
 __device__ __forceinline__ void wf_stage(T (*const (&dst)[NA])[kWT], const gptr<T> (&src)[NA],
                                          int one, const WEdge<T> (&edge)[NE], const WTile& w) {
@@ -184,17 +184,38 @@ __device__ __forceinline__ void wf_stage(T (*const (&dst)[NA])[kWT], const gptr<
                                        (lptr)((unsigned char*)edge[e].dst + h * 256), 4, 0, 0);
     }
   }
+  // A tile wholly inside the map whose rows start 16-byte aligned goes in
+  // 16-byte pieces, kVR rows per instruction (lane l: row l / (64 / kVR) of
+  // the group, piece l % (64 / kVR)); the rest dword by dword, clamped.
+  bool vec = w.i0 + kWT <= w.M && w.j0 + kWT <= w.N && (w.N * sizeof(T)) % 16 == 0;
 #pragma unroll
-  for (int q = 0; q < NA; ++q) {
-    for (int t = wv; t < kWT; t += kWWaves) {
+  for (int q = 0; q < NA; ++q) vec = vec && ((size_t)src[q] & 15) == 0;
+  if (vec) {
+    constexpr int kVR = 64 * 16 / (kWT * (int)sizeof(T));  // rows per instruction
+    const int sub = l / (64 / kVR), piece = l % (64 / kVR);
 #pragma unroll
-      for (int h = 0; h < kParts; ++h) {
-        // dword h * 64 + l of row t's kWT elements
-        const int dw = h * 64 + l, c = dw / kParts, part = dw % kParts;
-        bool ok;
-        const size_t at = wf_at(w.i0 + t, w.j0 + c, w.M, w.N, ok);
-        __builtin_amdgcn_global_load_lds((gbyte)src[q] + at * sizeof(T) + part * 4,
-                                         (lptr)((unsigned char*)&dst[q][t][0] + h * 256), 4, 0, 0);
+    for (int q = 0; q < NA; ++q) {
+      for (int g = wv; g < kWT / kVR; g += kWWaves) {
+        const int t = g * kVR + sub;
+        const size_t at = (size_t)(w.i0 + t) * w.N + w.j0;
+        __builtin_amdgcn_global_load_lds((gbyte)src[q] + at * sizeof(T) + piece * 16,
+                                         (lptr)&dst[q][g * kVR][0], 16, 0, 0);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      for (int t = wv; t < kWT; t += kWWaves) {
+#pragma unroll
+        for (int h = 0; h < kParts; ++h) {
+          // dword h * 64 + l of row t's kWT elements
+          const int dw = h * 64 + l, c = dw / kParts, part = dw % kParts;
+          bool ok;
+          const size_t at = wf_at(w.i0 + t, w.j0 + c, w.M, w.N, ok);
+          __builtin_amdgcn_global_load_lds((gbyte)src[q] + at * sizeof(T) + part * 4,
+                                           (lptr)((unsigned char*)&dst[q][t][0] + h * 256), 4, 0,
+                                           0);
+        }
       }
     }
   }
@@ -264,7 +285,7 @@ __device__ __forceinline__ void wf_store(T* out, const T (*src)[kWT], const WTil
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(kWThreads) k_wf_pivots(WArgs a) {
-  __shared__ T Us[kWT][kWT], Vs[kWT][kWT];
+  __shared__ __attribute__((aligned(16))) T Us[kWT][kWT], Vs[kWT][kWT];
   __shared__ T left[kWT], top[kWT], ul[kWT], vt[kWT];
   WTile w;
   if (!wf_tile<false>(a, w)) return;
