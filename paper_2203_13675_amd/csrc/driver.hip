@@ -358,8 +358,11 @@ static int engine_activate(lp_unwrap_ctx* ctx, const std::vector<int>& set, int*
   // round-robin over the 8 XCDs, so list position q runs on XCD q mod 8 (the
   // grid is a multiple of 8).  All column tiles of one row block go to one
   // XCD, consecutively, so the block's rows of X are re-read from that XCD's
-  // L2; row blocks are balanced over the XCDs largest first.  Unused slots
-  // hold -1.
+  // L2; row blocks are balanced over the XCDs largest first.  (Grouping the
+  // row blocks of one contraction length on few XCDs, so that each XCD
+  // fetches fewer basis tables, cut the counted traffic by 10 % but made the
+  // stages 27 % slower: short and long tiles no longer mix on an XCD.)
+  // Unused slots hold -1.
   int ndl[2] = {0, 0};
   for (int par = 0; par < 2; ++par) {
     int* out = hd + par * e.dlist_cap;
@@ -389,8 +392,14 @@ static int engine_activate(lp_unwrap_ctx* ctx, const std::vector<int>& set, int*
     size_t L = 0;
     for (int x = 0; x < 8; ++x) L = std::max(L, q[x].size());
     int len = 0;
-    for (size_t j = 0; j < L; ++j)
-      for (int x = 0; x < 8; ++x) out[len++] = j < q[x].size() ? q[x][j] : -1;
+    if (8 * (long long)L <= e.dlist_cap) {
+      for (size_t j = 0; j < L; ++j)
+        for (int x = 0; x < 8; ++x) out[len++] = j < q[x].size() ? q[x][j] : -1;
+    } else {
+      // the padded form would not fit: every tile once, in XCD order
+      for (int x = 0; x < 8; ++x)
+        for (int t : q[x]) out[len++] = t;
+    }
     ndl[par] = len;
   }
   const int nd = std::max(ndl[0], ndl[1]);
