@@ -141,10 +141,13 @@ __device__ __forceinline__ R2<T> ldrow(const T* __restrict__ a, int i, int j0, i
   return v;
 }
 
-// halo column of this lane (lane 0: j0 - 1, lane 63: j0 + 128, others none)
+// Halo column of this lane's halo load: lane 0 uses column j0 - 1, lane 63
+// column j0 + 128.  The other lanes' values are never used, but the load is
+// one instruction for the whole wave: they read the same two columns, so the
+// instruction touches only the two halo lines (a lane clamped to column 0
+// would fetch one more line of every row).
 __device__ __forceinline__ int halo_col(int j0) {
-  const int l = lane_id();
-  return l == 0 ? j0 - 1 : (l == 63 ? j0 + kTW : -1);
+  return lane_id() < 32 ? j0 - 1 : j0 + kTW;
 }
 
 template <typename T>
@@ -166,7 +169,7 @@ template <int TH, bool FULL, typename T, typename Ld, typename Mk, typename E>
 __device__ __forceinline__ void march_stencil(const TilePos& tp, const T* __restrict__ U,
                                               const T* __restrict__ V, Ld load, Mk make, E epi) {
   const int M = tp.M, N = tp.N, i0 = tp.i0, j0 = tp.j0, l = lane_id();
-  const int hj = halo_col(j0), uj = l == 0 ? j0 - 1 : -1;
+  const int hj = halo_col(j0), uj = j0 - 1;  // U's halo: column j0 - 1 (lane 0's), every lane
   const int ca = j0 + l, cb = j0 + 64 + l;
   using Raw = decltype(load(0, 0));
   struct Row {
