@@ -508,3 +508,25 @@ def test_batch_matches_single(ctx, pc):
                            outer_tol=0.0)
         assert maxdiff(host(phis[k]), host(single.phi)) <= 1e-4
         assert stats[k]["final_relres"] <= 1e-6
+
+
+@pytest.mark.parametrize("M, N", [(2304, 1024), (6144, 6144)])
+def test_batch_grouped_sums_match_single(ctx, M, N):
+    """Maps whose tile partials the finishing block cannot read in one round
+    (2304 x 1024: more than 512 stencil tiles at any tile height; 6144 x 6144:
+    also more than 2048 even/odd DCT tiles) take the grouped association of
+    the fused finishers.  It is a function of the map alone: the map's result
+    in a batch with small maps equals its single solve bit for bit."""
+    big, _ = synth.peaks_map(M, N, amplitude=40.0, sigma=0.3, seed=5)
+    small = [synth.peaks_map(m, n, amplitude=10.0, sigma=0.3, seed=6)[0]
+             for m, n in [(128, 128), (256, 384)]]
+    kw = dict(p=0.0, preconditioner="dct", precision="mixed", dct_mode="fp16_scaled", k_max=1,
+              outer_tol=0.0)
+    phis, rc, stats = ctx.batch([dev(big)] + [dev(s) for s in small], **kw)
+    single = ctx.solve(dev(big), **kw)
+    print("grouped sums", (M, N), "inner", stats[0]["inner_iters_total"],
+          single.stats["inner_iters_total"], "relres", stats[0]["final_relres"])
+    assert stats[0]["inner_iters_total"] == single.stats["inner_iters_total"]
+    assert np.array_equal(host(phis[0]), host(single.phi))
+    for s in stats:
+        assert s["final_relres"] <= 1e-6
