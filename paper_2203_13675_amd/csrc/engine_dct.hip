@@ -603,9 +603,9 @@ __global__ void __launch_bounds__(256, 2) k_e_dct_eo(DArgs a) {
       if (tid == 0) store_partial(a.P + 1 * a.pstride + g, vv[0]);
       if (a.fin_mode) {
         const int sl[1] = {1};
-        fused_finish<1>(Arrival{a.fcnt, a.gcnt, a.gsum, a.gstride, a.P, a.pstride}, sl,
-                        g - t_local, t_local, t_ndt, t_gbd, a.desc, a.ms, tm, kFinTail,
-                        a.fin_mode, 0, &fflag, fred);
+        fused_finish<kFinTail, 1>(Arrival{a.fcnt, a.gcnt, a.gsum, a.gstride, a.P, a.pstride}, sl,
+                                  g - t_local, t_local, t_ndt, t_gbd, a.desc, a.ms, tm,
+                                  a.fin_mode, 0, &fflag, fred);
       }
     }
   }

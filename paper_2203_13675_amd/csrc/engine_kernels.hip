@@ -745,8 +745,8 @@ __global__ void __launch_bounds__(64) k_e_spmv(EArgs A) {
     if (A.fuse_pw >= 0) {
       const MapDesc& dm = A.desc[tp.m];
       const int sl[1] = {0};
-      fused_finish<1>(arrival(A), sl, dm.tile0, g - dm.tile0, dm.ntiles, dm.gb, A.desc, A.ms,
-                      tp.m, kFinAlpha, kFinishNone, A.fuse_pw, &fflag, fred);
+      fused_finish<kFinAlpha, 1>(arrival(A), sl, dm.tile0, g - dm.tile0, dm.ntiles, dm.gb, A.desc,
+                                 A.ms, tp.m, kFinishNone, A.fuse_pw, &fflag, fred);
     }
   }
 }
@@ -852,8 +852,8 @@ __global__ void __launch_bounds__(64) k_e_update(EArgs A) {
     if (A.fuse_pw >= 0) {
       const MapDesc& dm = A.desc[tp.m];
       const int sl[2] = {0, 1};
-      fused_finish<2>(arrival(A), sl, dm.tile0, g - dm.tile0, dm.ntiles, dm.gb, A.desc, A.ms,
-                      tp.m, kFinUpdate, kFinishNone, A.fuse_pw, &fflag, fred);
+      fused_finish<kFinUpdate, 2>(arrival(A), sl, dm.tile0, g - dm.tile0, dm.ntiles, dm.gb, A.desc,
+                                  A.ms, tp.m, kFinishNone, A.fuse_pw, &fflag, fred);
     }
   }
 }
@@ -970,8 +970,8 @@ __global__ void __launch_bounds__(64) k_e_twocolor(EArgs A, T c) {
       if (A.fin_mode) {
         const MapDesc& dm = A.desc[tp.m];
         const int sl[1] = {1};
-        fused_finish<1>(arrival(A), sl, dm.tile0, g - dm.tile0, dm.ntiles, dm.gb, A.desc, A.ms,
-                        tp.m, kFinTailS, A.fin_mode, 0, &fflag, fred);
+        fused_finish<kFinTailS, 1>(arrival(A), sl, dm.tile0, g - dm.tile0, dm.ntiles, dm.gb, A.desc,
+                                   A.ms, tp.m, A.fin_mode, 0, &fflag, fred);
       }
     }
   }

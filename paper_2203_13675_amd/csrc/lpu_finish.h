@@ -199,8 +199,11 @@ __device__ inline void finish_map(const MapDesc* __restrict__ desc, MapState* ms
   const MapDesc& d = desc[m];
   double v[3] = {0.0, 0.0, 0.0};
   if (op == kFinInit) {
-    const int sl[3] = {0, 1, 2};
-    fin_sums<GROUPS, 3>(src, d.tile0, d.ntiles, d.gb, sl, v, smem);
+    // three slots: standalone finishers only (fused_finish rejects the op)
+    if constexpr (!GROUPS) {
+      const int sl[3] = {0, 1, 2};
+      fin_sums<GROUPS, 3>(src, d.tile0, d.ntiles, d.gb, sl, v, smem);
+    }
   } else if (op == kFinAlpha) {
     const int sl[1] = {0};
     double w[1];
@@ -373,15 +376,16 @@ __device__ inline int last_arrival(const Arrival& a, const int (&slots)[NS], int
 // stored, and in the block that completes the map, the map's finisher (then
 // the map counter is rearmed).  flag and smem (3 * blockDim.x / 64 doubles)
 // are shared memory.
-template <int NS>
+template <int OP, int NS>
 __device__ inline void fused_finish(const Arrival& a, const int (&slots)[NS], int first, int local,
                                     int total, int gbase, const MapDesc* desc, MapState* ms, int m,
-                                    int op, int mode, int pointwise, int* flag, double* smem) {
+                                    int mode, int pointwise, int* flag, double* smem) {
+  static_assert(OP != kFinInit, "group sums hold two slots; the set-up sums are not fused");
   const int kind = last_arrival<NS>(a, slots, first, m, local, total, gbase, flag);
   if (kind == kArrNotLast) return;
   const FinSrc src{a.P, a.pstride, a.gsum, a.gstride};
-  if (kind == kArrFlat) finish_map<false>(desc, ms, src, m, op, mode, pointwise, smem);
-  else finish_map<true>(desc, ms, src, m, op, mode, pointwise, smem);
+  if (kind == kArrFlat) finish_map<false>(desc, ms, src, m, OP, mode, pointwise, smem);
+  else finish_map<true>(desc, ms, src, m, OP, mode, pointwise, smem);
   if (threadIdx.x == 0) __hip_atomic_store(a.fcnt + m, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
