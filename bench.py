@@ -233,6 +233,19 @@ def main():
     }
     if tune:
         out["autotune"] = tune
+    if "dct" in ktimes and ktimes["dct"]["ms"] > 0:
+        # The DCT preconditioner as four dense contractions moves 24 B/px per
+        # application on this path (tables aside); a fast O(n log n) transform
+        # would need at least one read of r and one write of s, 8 B/px.  Time
+        # that floor would take at HBM peak, against the stages' measured time.
+        kd = ktimes["dct"]
+        floor_ms = kd["bytes"] * (8.0 / 24.0) / (PEAK_HBM_GBS * 1e9) * 1e3
+        out["dct_fast_transform_floor"] = {
+            "floor_ms_per_step": floor_ms, "dct_ms_per_step": kd["ms"],
+            "frac": floor_ms / kd["ms"],
+            "note": "HBM time of 8 B/px per preconditioner application (read r, write s) at "
+                    "8 TB/s over the step's applications, against the four contraction stages' "
+                    "measured time"}
     # How full the PCG launches can be.  Every launch of an iteration covers
     # the maps still iterating; the batch needs at least as many iteration
     # launches as its slowest map has iterations, however the maps are
