@@ -754,8 +754,10 @@ __global__ void __launch_bounds__(64) k_e_spmv(EArgs A) {
 // update: r -= alpha q (the step alpha d is added to x by the next SpMV), or,
 // when l is a multiple of the replacement period, x_new = x + alpha d into
 // the other x buffer and r = b - A x_new; pointwise s; partials r.r, r.s
+// Five waves per SIMD fit without spills (96 VGPRs); the update is a short
+// stream, so the extra wave in flight helps a little (about 1 %).
 template <typename T, int PC, int TH>
-__global__ void __launch_bounds__(64) k_e_update(EArgs A) {
+__global__ void __launch_bounds__(64, 5) k_e_update(EArgs A) {
   __shared__ double fred[3];
   __shared__ int fflag;
   TILE_LOOP(A) {
