@@ -408,7 +408,7 @@ __global__ void __launch_bounds__(kWThreads) k_wf_forward(WArgs a) {
   // lane 0 keeps the values above the tile, which its reads of the row above
   // its own fetched.
   if (threadIdx.x < 64) {
-  T y_own = left[l], vn_own = T(0), uwest = ul[l];
+  T y_own = left[l], uwest = ul[l];
   T ra[kWR], rr[kWR], va[kWR], vv[kWR], pp[kWR], uu[kWR];
   auto fetch = [&](int u, int col) {
     ra[u] = sm[0][l][col], rr[u] = sm[0][l + 1][col];
@@ -417,19 +417,22 @@ __global__ void __launch_bounds__(kWThreads) k_wf_forward(WArgs a) {
   };
 #pragma unroll
   for (int u = 0; u < kWR; ++u) fetch(u, (u - l) & (kWT - 1));
+  // The north coupling V(l - 1, c) a lane uses at a step is lane l - 1's
+  // own operand of the previous step, shifted at the end of that step before
+  // its slot is refilled (lane 0: the row above's, from the next slot).
+  T vn = va[0];
   for (int k0 = 0; k0 < kWSteps; k0 += kWR) {
 #pragma unroll
     for (int u = 0; u < kWR; ++u) {
       const int c = k0 + u - l;
       const T yup = from_prev_lane(ra[u], y_own);  // lane 0: y of the row above, column k
-      const T vn = from_prev_lane(va[u], vn_own);
       if (c >= 0 && c < kWT) {
         const T v = (rr[u] + vn * yup + uwest * y_own) * pp[u];  // pp = 1 / p
         sm[0][l + 1][c] = v;
         y_own = v;
-        vn_own = vv[u];
         uwest = uu[u];
       }
+      vn = from_prev_lane(va[(u + 1) % kWR], vv[u]);
       fetch(u, (c + kWR) & (kWT - 1));
     }
   }
