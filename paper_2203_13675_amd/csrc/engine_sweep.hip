@@ -474,6 +474,14 @@ __global__ void __launch_bounds__(kWThreads) k_wf_backward(WArgs a) {
     wf_stage<T, 4, 2>(dst, src, 1, edge, w);
   }
   wf_pivot_pairs<T>(pu);
+  // r for the closing r^T s (wave wv: rows wv, wv + kWWaves, ...), requested
+  // before the wavefront so its latency hides behind the chain
+  constexpr int kRows = kWT / kWWaves;
+  const int j = w.j0 + l;
+  const int dt0 = a.desc[w.m].dtile0;
+  T rv[kRows];
+#pragma unroll
+  for (int u = 0; u < kRows; ++u) rv[u] = wf_ld<T>(r, w.i0 + wv + u * kWWaves, j, M, N, T(0));
   // wave 0, lane l owns tile row 63 - l; at step k it computes column
   // 63 - (k - l); operands read kWR steps ahead, and lane 0's south
   // neighbours (the row below the tile) carried as in the forward solve
@@ -505,16 +513,10 @@ __global__ void __launch_bounds__(kWThreads) k_wf_backward(WArgs a) {
   // z back to y, s = c z, and the tile's partial of r^T s (wave wv: rows wv,
   // wv + kWWaves, ...; the waves' sums added in a fixed order)
   const T scale = a.ssor ? (T)(2.0 - a.omega) : T(1);
-  const int j = w.j0 + l;
   double part = 0.0;
-  constexpr int kRows = kWT / kWWaves;
-  T z[kRows], rv[kRows];
+  T z[kRows];
 #pragma unroll
-  for (int u = 0; u < kRows; ++u) {
-    const int t = wv + u * kWWaves;
-    z[u] = Yz[t][l];
-    rv[u] = wf_ld<T>(r, w.i0 + t, j, M, N, T(0));
-  }
+  for (int u = 0; u < kRows; ++u) z[u] = Yz[wv + u * kWWaves][l];
 #pragma unroll
   for (int u = 0; u < kRows; ++u) {
     const int i = w.i0 + wv + u * kWWaves;
@@ -533,7 +535,7 @@ __global__ void __launch_bounds__(kWThreads) k_wf_backward(WArgs a) {
     double tot = 0.0;
 #pragma unroll
     for (int k = 0; k < kWWaves; ++k) tot += red[k];
-    store_partial(a.P + 1 * a.pstride + a.desc[w.m].dtile0 + w.local, tot);
+    store_partial(a.P + 1 * a.pstride + dt0 + w.local, tot);
   }
 }
 
