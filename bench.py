@@ -90,6 +90,39 @@ def parse():
     return ap.parse_args()
 
 
+def dct_floor_record(dct_bytes, dct_ms):
+    """The DCT preconditioner as four dense contractions moves 24 B/px per
+    application on the benchmark path (tables aside); a fast O(n log n)
+    transform needs at least one read of r and one write of s, 8 B/px.  The
+    time that floor takes at HBM peak, against the stages' measured time
+    (dct_bytes: the stages' algorithmic bytes over the step)."""
+    floor_ms = dct_bytes * (8.0 / 24.0) / (PEAK_HBM_GBS * 1e9) * 1e3
+    return {"floor_ms_per_step": floor_ms, "dct_ms_per_step": dct_ms, "frac": floor_ms / dct_ms,
+            "note": "HBM time of 8 B/px per preconditioner application (read r, write s) at "
+                    "8 TB/s over the step's applications, against the four contraction stages' "
+                    "measured time"}
+
+
+def iteration_record(shapes, its, n_spmv):
+    """How full the PCG launches can be.  Every launch of an iteration covers
+    the maps still iterating; the batch needs at least as many iteration
+    launches as its slowest map has iterations, however the maps are
+    scheduled, so sum(px * iters) / (max iters * total px) bounds the mean
+    fraction of the batch's pixels per launch."""
+    px_m = [m * n for m, n in shapes]
+    total_px = sum(px_m)
+    work = sum(p * i for p, i in zip(px_m, its))
+    return {
+        "per_map": {"min": min(its), "median": float(np.median(its)),
+                    "p90": float(np.percentile(its, 90)), "max": max(its)},
+        "spmv_launches": n_spmv,
+        "launch_fill": work / (n_spmv * total_px) if n_spmv else None,
+        "launch_fill_bound": work / (max(its) * total_px) if max(its) > 0 else None,
+        "note": "launch_fill: pixel-iterations / (SpMV launches x batch pixels); "
+                "launch_fill_bound: the same with the slowest map's iteration count as the "
+                "launch count, the best any schedule of these maps reaches"}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -234,36 +267,10 @@ def main():
     if tune:
         out["autotune"] = tune
     if "dct" in ktimes and ktimes["dct"]["ms"] > 0:
-        # The DCT preconditioner as four dense contractions moves 24 B/px per
-        # application on this path (tables aside); a fast O(n log n) transform
-        # would need at least one read of r and one write of s, 8 B/px.  Time
-        # that floor would take at HBM peak, against the stages' measured time.
-        kd = ktimes["dct"]
-        floor_ms = kd["bytes"] * (8.0 / 24.0) / (PEAK_HBM_GBS * 1e9) * 1e3
-        out["dct_fast_transform_floor"] = {
-            "floor_ms_per_step": floor_ms, "dct_ms_per_step": kd["ms"],
-            "frac": floor_ms / kd["ms"],
-            "note": "HBM time of 8 B/px per preconditioner application (read r, write s) at "
-                    "8 TB/s over the step's applications, against the four contraction stages' "
-                    "measured time"}
-    # How full the PCG launches can be.  Every launch of an iteration covers
-    # the maps still iterating; the batch needs at least as many iteration
-    # launches as its slowest map has iterations, however the maps are
-    # scheduled, so sum(px * iters) / (max iters * total px) bounds the mean
-    # fraction of the batch's pixels per launch.
-    px_m = [m * n for m, n in shapes]
-    its = [s["inner_iters_total"] for s in stats]
-    work = sum(p * i for p, i in zip(px_m, its))
-    n_spmv = ktimes.get("spmv", {}).get("launches", 0)
-    out["iterations"] = {
-        "per_map": {"min": min(its), "median": float(np.median(its)),
-                    "p90": float(np.percentile(its, 90)), "max": max(its)},
-        "spmv_launches": n_spmv,
-        "launch_fill": work / (n_spmv * total_px) if n_spmv else None,
-        "launch_fill_bound": work / (max(its) * total_px) if max(its) > 0 else None,
-        "note": "launch_fill: pixel-iterations / (SpMV launches x batch pixels); "
-                "launch_fill_bound: the same with the slowest map's iteration count as the "
-                "launch count, the best any schedule of these maps reaches"}
+        out["dct_fast_transform_floor"] = dct_floor_record(ktimes["dct"]["bytes"],
+                                                           ktimes["dct"]["ms"])
+    out["iterations"] = iteration_record(shapes, [s["inner_iters_total"] for s in stats],
+                                         ktimes.get("spmv", {}).get("launches", 0))
 
     gpu_phis = [ph.cpu().numpy() for ph in phis]
     if a.fp64_compare and not a.profile:

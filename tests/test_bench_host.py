@@ -1,6 +1,7 @@
 """Host-side logic of bench.py (no GPU): the measured-traffic field is taken
 from the committed counter summary only while every source file it was
-measured with is unchanged, and the multi-GPU request is refused."""
+measured with is unchanged, the multi-GPU request is refused, and the
+launch-fill and fast-transform-floor records follow their definitions."""
 import hashlib
 import importlib.util
 import os
@@ -71,3 +72,26 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode != 0
     assert "one GPU" in r.stderr
+
+
+def test_iteration_record():
+    bench = load_bench()
+    # maps of 100 and 200 px, 5 and 10 iterations, 12 SpMV launches
+    rec = bench.iteration_record([(10, 10), (10, 20)], [5, 10], 12)
+    work, total = 100 * 5 + 200 * 10, 300
+    assert rec["launch_fill"] == pytest.approx(work / (12 * total))
+    assert rec["launch_fill_bound"] == pytest.approx(work / (10 * total))
+    assert rec["per_map"]["max"] == 10 and rec["per_map"]["min"] == 5
+    # no schedule issues fewer launches than the slowest map's iterations, so
+    # a measured fill never exceeds the bound; equal maps fill every launch
+    assert rec["launch_fill"] <= rec["launch_fill_bound"]
+    assert bench.iteration_record([(8, 8), (4, 16)], [7, 7], 7)["launch_fill"] == pytest.approx(1.0)
+    assert bench.iteration_record([(8, 8)], [3], 0)["launch_fill"] is None
+
+
+def test_dct_floor_record():
+    bench = load_bench()
+    # 24 GB of four-stage traffic is 8 GB at the fast-transform floor: 1 ms at 8 TB/s
+    rec = bench.dct_floor_record(24e9, 100.0)
+    assert rec["floor_ms_per_step"] == pytest.approx(1.0)
+    assert rec["frac"] == pytest.approx(0.01)
