@@ -31,6 +31,7 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 PEAK_BF16_TFLOPS = 2500.0
 PEAK_FP16_TFLOPS = 2500.0
+PEAK_FP64_TFLOPS = 78.6  # vector FMA units: the plain FP64 path's DCT stages run there
 # measured HBM traffic per launch (rocprofv3 FETCH_SIZE / WRITE_SIZE passes,
 # scaled by a plain copy), valid while the kernel sources hash as recorded
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "traffic_batch256_fp16.txt")
@@ -72,9 +73,11 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--maps", type=int, default=256)
     ap.add_argument("--workload", default="batch256",
-                    choices=["batch256", "peaks1024", "gauss2048_hole", "ramp4096"],
+                    choices=["batch256", "peaks64", "peaks1024", "gauss2048_hole", "ramp4096"],
                     help="batch256 (default, the benchmark line) or one of the single-map "
                          "workloads, run through the same path for profiling")
+    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"],
+                    help="mixed (default) or the plain FP64 path (the 64x64 case's setting)")
     ap.add_argument("--outer", type=int, default=10)
     ap.add_argument("--dct-mode", default="fp16_scaled")
     ap.add_argument("--fp64-compare", type=int, default=1,
@@ -160,7 +163,8 @@ def main():
     phis = [torch.zeros_like(t) for t in psis]
     opts = dict(p=0.0, eps=0.01, preconditioner="dct", tol=1e-6)
     ctx = Context(0)
-    o = default_options(precision="mixed", dct_mode=a.dct_mode, k_max=a.outer, outer_tol=0.0)
+    o = default_options(precision=a.precision, dct_mode=a.dct_mode, k_max=a.outer, outer_tol=0.0)
+    fp64 = a.precision == "fp64"
 
     def step():
         return ctx.batch(psis, masks, phis=phis, options=o, **opts)
@@ -222,7 +226,8 @@ def main():
         name, kt = dom
         launches = max(kt["launches"], 1)
         per_launch_s = kt["ms"] / 1e3 / launches
-        traffic = measured_traffic(name, a.dct_mode, a.maps) if a.workload == "batch256" else None
+        traffic = (measured_traffic(name, a.dct_mode, a.maps)
+                   if a.workload == "batch256" and not fp64 else None)
         common = {"kernel": name, "traffic": traffic, "traffic_unit": "bytes per launch",
                   "alg_bytes_per_launch": kt["bytes"] / launches,
                   "alg_flops_per_launch": kt["flops"] / launches,
@@ -230,18 +235,20 @@ def main():
         # the binding roof is the one whose time at peak is longer: MFMA when
         # the launch's flops per algorithmic byte exceed the ridge point
         # (peak flops / peak bandwidth), HBM otherwise
-        ridge = PEAK_FP16_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9)
+        # (on the plain FP64 path the DCT stages run on the FP64 FMA units)
+        peak_flops = PEAK_FP64_TFLOPS if fp64 else PEAK_FP16_TFLOPS
+        ridge = peak_flops * 1e12 / (PEAK_HBM_GBS * 1e9)
         intensity = kt["flops"] / kt["bytes"] if kt["bytes"] > 0 else float("inf")
         common["flops_per_byte"] = intensity
         common["ridge_flops_per_byte"] = ridge
         if kt["flops"] > 0:
             tf = kt["flops"] / launches / per_launch_s / 1e12
-            common["mfma_achieved_tflops"] = tf
-            common["mfma_frac"] = tf / PEAK_FP16_TFLOPS
+            common["fma_achieved_tflops" if fp64 else "mfma_achieved_tflops"] = tf
+            common["fma_frac" if fp64 else "mfma_frac"] = tf / peak_flops
         if kt["flops"] > 0 and intensity >= ridge:
             ach = kt["flops"] / launches / per_launch_s / 1e12
-            roofline = {"bound": "mfma", "achieved": ach, "peak": PEAK_FP16_TFLOPS,
-                        "unit": "TFLOP/s", "frac": ach / PEAK_FP16_TFLOPS, **common}
+            roofline = {"bound": "alu" if fp64 else "mfma", "achieved": ach, "peak": peak_flops,
+                        "unit": "TFLOP/s", "frac": ach / peak_flops, **common}
         else:
             ach = kt["bytes"] / launches / per_launch_s / 1e9
             roofline = {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS,
@@ -251,12 +258,16 @@ def main():
         "metric": "Mpixel/s unwrapped at 1e-6 rel. residual; batched mixed-prec vs plain FP64",
         "value": value, "unit": "Mpixel/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
         "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "vs_baseline": None, "dtype": "f64" if fp64 else "f32", "data": "synthetic",
         "config": {"workload": desc,
                    "maps": len(shapes), "total_pixels": total_px, "outer_iters": a.outer,
-                   "precision": "mixed: f32 CG vectors, %s DCT on MFMA, f64 dots and "
-                                "residual refinement" % a.dct_mode},
+                   "precision": ("fp64: the plain path, FP64 throughout" if fp64 else
+                                 "mixed: f32 CG vectors, %s DCT on MFMA, f64 dots and "
+                                 "residual refinement" % a.dct_mode)},
         "pcg_iters_per_step": inner, "cg_iters_per_s": inner / dt,
+        # iterations are issued in rounds over every map still iterating, so
+        # the slowest map's count is the number of rounds
+        "us_per_iteration_round": dt * 1e6 / max(1, max(s["inner_iters_total"] for s in stats)),
         "worst_final_relres": worst_relres,
         "kernel_ms_per_step": warm_split,
         "kernel_classes": classes,
@@ -266,14 +277,14 @@ def main():
     }
     if tune:
         out["autotune"] = tune
-    if "dct" in ktimes and ktimes["dct"]["ms"] > 0:
+    if "dct" in ktimes and ktimes["dct"]["ms"] > 0 and not fp64 and a.dct_mode == "fp16_scaled":
         out["dct_fast_transform_floor"] = dct_floor_record(ktimes["dct"]["bytes"],
                                                            ktimes["dct"]["ms"])
     out["iterations"] = iteration_record(shapes, [s["inner_iters_total"] for s in stats],
                                          ktimes.get("spmv", {}).get("launches", 0))
 
     gpu_phis = [ph.cpu().numpy() for ph in phis]
-    if a.fp64_compare and not a.profile:
+    if a.fp64_compare and not a.profile and not fp64:
         o64 = default_options(precision="fp64", k_max=a.outer, outer_tol=0.0)
         # the same batch in one call at FP64: the precision's share of the gain
         ctx.batch(psis, masks, phis=[torch.zeros_like(t) for t in psis], options=o64, **opts)

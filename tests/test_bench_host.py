@@ -95,3 +95,13 @@ def test_dct_floor_record():
     rec = bench.dct_floor_record(24e9, 100.0)
     assert rec["floor_ms_per_step"] == pytest.approx(1.0)
     assert rec["frac"] == pytest.approx(0.01)
+
+
+def test_small_fp64_case_parses(monkeypatch):
+    bench = load_bench()
+    monkeypatch.setattr(sys, "argv", ["bench.py", "--workload", "peaks64", "--precision", "fp64"])
+    a = bench.parse()
+    assert (a.workload, a.precision, a.gpus) == ("peaks64", "fp64", 1)
+    monkeypatch.setattr(sys, "argv", ["bench.py"])
+    a = bench.parse()
+    assert (a.workload, a.precision) == ("batch256", "mixed")
