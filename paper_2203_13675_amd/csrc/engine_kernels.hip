@@ -686,6 +686,14 @@ __global__ void __launch_bounds__(64) k_e_resid(EArgs A) {
   }
 }
 
+// Non-temporal accesses for data whose next use is a later iteration (the
+// iterate, the new direction) or that is dead after this read (q in the
+// update): they leave the caches to what the next kernel reads.
+template <typename T>
+__device__ __forceinline__ T ld_stream(const T* p) { return __builtin_nontemporal_load(p); }
+template <typename T>
+__device__ __forceinline__ void st_stream(T* p, T v) { __builtin_nontemporal_store(v, p); }
+
 // spmv: d_new = s + beta d_old; q = A d_new; partial d^T q.  Also adds the
 // previous iteration's step to the iterate, x += alpha_p d_old (the update
 // leaves it here: x is first needed again by a replacement or at the end, and
@@ -729,15 +737,15 @@ __global__ void __launch_bounds__(64) k_e_spmv(EArgs A) {
           v.w = PC == kPcJacobi ? aux[p] : T(1);
           v.d = ok ? d0 : T(0);
           v.x = T(0);
-          if (pend && i >= tp.i0 && i < i_end && j >= tp.j0 && j < tp.j0 + kTW) v.x = x[p];
+          if (pend && i >= tp.i0 && i < i_end && j >= tp.j0 && j < tp.j0 + kTW) v.x = ld_stream(x + p);
           return v;
         },
         [&](const R4<T>& v) { return (PC == kPcJacobi ? v.s * v.w : v.s) + beta * v.d; },
         [&](int i, int j, T dv, T qv, const R4<T>& raw) {
           const size_t p = (size_t)i * N + j;
-          dnew[p] = dv;
+          st_stream(dnew + p, dv);
           q[p] = qv;
-          if (pend) x[p] = raw.x + ap * raw.d;
+          if (pend) st_stream(x + p, raw.x + ap * raw.d);
           sdq += (double)dv * (double)qv;
         });
     sdq = wave_sum(sdq);
@@ -821,7 +829,7 @@ __global__ void __launch_bounds__(64, 5) k_e_update(EArgs A) {
             const size_t row = (size_t)min(tp.i0 + k0 + c, M - 1) * N;
             const size_t pa = row + ja, pb = row + jb;
             rv[c][0] = r[pa], rv[c][1] = r[pb];
-            qv[c][0] = q[pa], qv[c][1] = q[pb];
+            qv[c][0] = ld_stream(q + pa), qv[c][1] = ld_stream(q + pb);
             wv[c][0] = PC == kPcJacobi ? aux[pa] : T(1);
             wv[c][1] = PC == kPcJacobi ? aux[pb] : T(1);
           }
