@@ -37,6 +37,7 @@ void e_dct_stage(hipStream_t st, const Engine& e, int ndtiles, int stage, int ex
                  const void* X, void* Out, const void* rvec, int fin_mode);
 int egrid(const Engine& e, int ntiles);
 int dct_grid_for(const Engine& e, int ndtiles);
+bool dct_wide_for(const Engine& e, int ndtiles, int kind);
 template <typename T> void e_pivots(hipStream_t, const Engine&, int, bool, double);
 void wf_shape(int M, int N, int* diags, int* len);
 template <typename T> void e_tc_pivots(hipStream_t, const Engine&, int, bool, double);
@@ -208,7 +209,7 @@ static int engine_setup(lp_unwrap_ctx* ctx, int n, const lpu_map* maps, int elem
     // pinned staging (counts, active maps, stencil tiles, the two DCT
     // lists), so the first three go up in one copy
     const long long dcap = (long long)dtiles + 8LL * (n + 1) * 256 + 64;
-    const size_t list_ints = kListHead + (size_t)n + (size_t)tiles + 2 * (size_t)dcap;
+    const size_t list_ints = kListHead + (size_t)n + (size_t)tiles + 4 * (size_t)dcap;
     A((void**)&e.counts, 4 * list_ints);
     if (ok) {
       e.mact = e.counts + kListHead;
@@ -363,9 +364,14 @@ static int engine_activate(lp_unwrap_ctx* ctx, const std::vector<int>& set, int*
   // fetches fewer basis tables, cut the counted traffic by 10 % but made the
   // stages 27 % slower: short and long tiles no longer mix on an XCD.)
   // Unused slots hold -1.
-  int ndl[2] = {0, 0};
-  for (int par = 0; par < 2; ++par) {
-    int* out = hd + par * e.dlist_cap;
+  // The even/odd kernels also take wide tiles (two neighbouring column
+  // tiles of a row block, named by the left one; the last one of a row
+  // block alone when it has no partner): lists 2 and 3, built the same way.
+  int ndl[4] = {0, 0, 0, 0};
+  const int nlists = e.dct_trows == 128 ? 4 : 2;
+  for (int li = 0; li < nlists; ++li) {
+    const int par = li & 1, step = li < 2 ? 1 : 2;
+    int* out = hd + li * e.dlist_cap;
     struct Unit {
       int tile0, tr, tc;
       long long w;
@@ -386,7 +392,7 @@ static int engine_activate(lp_unwrap_ctx* ctx, const std::vector<int>& set, int*
       int x = 0;
       for (int k = 1; k < 8; ++k)
         if (load[k] < load[x]) x = k;
-      for (int ct = 0; ct < u.tc; ++ct) q[x].push_back(u.tile0 + ct * u.tr);
+      for (int ct = 0; ct < u.tc; ct += step) q[x].push_back(u.tile0 + ct * u.tr);
       load[x] += u.w;
     }
     size_t L = 0;
@@ -400,7 +406,7 @@ static int engine_activate(lp_unwrap_ctx* ctx, const std::vector<int>& set, int*
       for (int x = 0; x < 8; ++x)
         for (int t : q[x]) out[len++] = t;
     }
-    ndl[par] = len;
+    ndl[li] = len;
   }
   const int nd = std::max(ndl[0], ndl[1]);
   int nm = 0;
@@ -410,13 +416,15 @@ static int engine_activate(lp_unwrap_ctx* ctx, const std::vector<int>& set, int*
   hc[1] = ndl[0];
   hc[2] = nm;
   hc[3] = ndl[1];
+  hc[5] = ndl[2];
+  hc[7] = ndl[3];
   // counts, maps and stencil tiles in one copy, then each DCT list
   const size_t head = (size_t)kListHead + (size_t)e.cap_maps + (size_t)nt;
   LPU_HIP_CHECK(ctx, hipMemcpyAsync(e.counts, hc, 4 * head, hipMemcpyHostToDevice, st));
-  for (int par = 0; par < 2; ++par)
-    if (ndl[par])
-      LPU_HIP_CHECK(ctx, hipMemcpyAsync(e.dact + par * e.dlist_cap, hd + par * e.dlist_cap,
-                                        4 * (size_t)ndl[par], hipMemcpyHostToDevice, st));
+  for (int li = 0; li < nlists; ++li)
+    if (ndl[li])
+      LPU_HIP_CHECK(ctx, hipMemcpyAsync(e.dact + li * e.dlist_cap, hd + li * e.dlist_cap,
+                                        4 * (size_t)ndl[li], hipMemcpyHostToDevice, st));
   LPU_HIP_CHECK(ctx, hipEventRecord(ctx->list_event, st));
   ctx->list_event_live = true;
   *ntiles = nt;
@@ -523,6 +531,7 @@ struct Pcg {
     for (int chunk = 8; chunk >= 1; chunk >>= 1) {
       if (K < chunk) continue;
       const int key[kGraphKey] = {egrid(e, nt), pointwise() ? 0 : dct_grid_for(e, nd),
+                                  pc == kPcDct && dct_wide_for(e, nd, dct_kind) ? 1 : 0,
                                   sweep ? nm : 0, sweep ? (e.wf_diags << 16) | e.wf_len : 0,
                                   pc, dct_kind,
                                   (int)sizeof(T), e.th, om[0], om[1], chunk};

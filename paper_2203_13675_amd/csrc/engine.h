@@ -118,8 +118,9 @@ struct Engine {
   int* tile_map = nullptr;   // global stencil tile -> map
   int* dtile_map = nullptr;  // global DCT tile -> map
   int* act = nullptr;        // active stencil tiles
-  int* dact = nullptr;       // active DCT tiles: two XCD-ordered lists (see driver)
-  long long dlist_cap = 0;   // capacity of each of the two DCT lists
+  int* dact = nullptr;       // active DCT tiles: XCD-ordered lists of narrow tiles for the
+                             // two stage parities, then of wide tiles (see driver)
+  long long dlist_cap = 0;   // capacity of each of the four DCT lists
   int dct_trows = kDT;       // DCT output tile rows (64 dense, 128 even/odd)
   int* mact = nullptr;       // active maps (sweep kernels)
   int* fcnt = nullptr;       // per-map arrival counters of the fused finishers (zero between launches)
@@ -128,8 +129,9 @@ struct Engine {
   long long gstride = 0;
   EoTile* eot = nullptr;     // even/odd DCT tile records, [parity][global DCT tile]
   int* counts = nullptr;     // [0] active tiles, [1] DCT list (even stages), [2] active
-                             // maps, [3] DCT list (odd stages); kListHead ints, followed
-                             // in the same allocation by mact, act and dact
+                             // maps, [3] DCT list (odd stages), [5] and [7] the wide-tile
+                             // lists; kListHead ints, followed in the same allocation by
+                             // mact, act and dact
   int* hlist = nullptr;      // pinned staging for counts and the lists, same layout
   // FP64 arrays
   double* dx = nullptr;

@@ -103,9 +103,9 @@ namespace lpu {
 
 // Executable graph of one PCG iteration for one launch shape; valid until the
 // engine is laid out again (the cache is emptied by every engine set-up).
-constexpr int kGraphKey = 11;
+constexpr int kGraphKey = 12;
 struct GraphEntry {
-  int key[kGraphKey];  // launch shapes, preconditioner and its parameters, precision,
+  int key[kGraphKey];  // launch shapes, DCT tile width, preconditioner and its parameters, precision,
                        // tile height, iterations per graph
   hipGraphExec_t exec;
 };

@@ -516,6 +516,26 @@ def test_batch_matches_single(ctx, pc, precision):
         assert stats[k]["final_relres"] <= 1e-6
 
 
+def test_batch_wide_dct_tiles_match_single(ctx):
+    """A batch with more than 512 narrow even/odd DCT tiles per stage runs the
+    first three DCT stages of its large launches on wide tiles (128 output
+    pairs, among them tiles without a partner: sides 128 and 384), while each
+    map solved alone runs on narrow tiles.  Per output the MFMAs take the same
+    K chunks in the same order, so the results agree bit for bit."""
+    shapes = [(1024, 1024)] * 7 + [(768, 384), (384, 1024), (128, 512), (1024, 768), (512, 1024)]
+    narrow = sum((m // 128) * (n // 128) for m, n in shapes)
+    assert narrow > 512  # the batch's first launches take wide tiles
+    maps = synth.batch_maps(sides=shapes, seed=91)
+    kw = dict(p=0.0, preconditioner="dct", precision="mixed", dct_mode="fp16_scaled", k_max=2,
+              outer_tol=0.0)
+    phis, rc, stats = ctx.batch([dev(p) for p, _ in maps], **kw)
+    for k, (p, _) in enumerate(maps):
+        single = ctx.solve(dev(p), **kw)
+        assert stats[k]["inner_iters_total"] == single.stats["inner_iters_total"], shapes[k]
+        assert np.array_equal(host(phis[k]), host(single.phi)), shapes[k]
+        assert stats[k]["final_relres"] <= 1e-6
+
+
 @pytest.mark.parametrize("M, N", [(2304, 1024), (6144, 6144)])
 def test_batch_grouped_sums_match_single(ctx, M, N):
     """Maps whose tile partials the finishing block cannot read in one round
