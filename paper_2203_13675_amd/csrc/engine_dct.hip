@@ -39,6 +39,7 @@ struct DArgs {
   int stage, expect;
   int trows;  // output tile rows: 64 (dense kernels) or 128 (even/odd kernels)
   int cidx;   // counts[] slot holding the length of `dact`
+  int dact_cap;  // entries of `dact` (its capacity)
   int *fcnt, *gcnt;  // arrival counters of the fused finisher
   double* gsum;      // its group sums (rows of gstride)
   long long gstride;
@@ -114,9 +115,12 @@ template <int SPLIT>
 __global__ void __launch_bounds__(256) k_e_dct_mfma(DArgs a) {
   __shared__ double red[4];
   const int nact = a.counts[a.cidx];
+  // the block's first list entry is requested with the list's length
+  const int g_first = a.dact[min((int)blockIdx.x, max(a.dact_cap - 1, 0))];
+  __asm__ volatile("" ::"s"(nact), "s"(g_first));  // both loads issued before the loop test
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int t_ = blockIdx.x; t_ < nact; t_ += gridDim.x) {
-    const int g = a.dact[t_];
+    const int g = t_ == (int)blockIdx.x ? g_first : a.dact[t_];
     if (g < 0) continue;  // padding slot of the XCD-ordered list
     const DTile t = dtile(a, g);
     if (!t.ok) continue;  // uniform over the block
@@ -284,7 +288,7 @@ typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
 // half the re-reads of X and less LDS traffic per output.  It pays on
 // launches of many tiles only (half as many tiles to spread over the CUs):
 // the first three stages of the batch's launches of at least 1024 list
-// positions take 6-9 % less time, those of a 4096 x 4096 map 12 % less.  A
+// positions take 6-9 % less time, those of a 4096 x 4096 map 15 % less.  A
 // wide tile is named by its left narrow tile; where the map has no right
 // partner (h an odd multiple of 64) it stages its own table rows twice and
 // stores the left half only.  Per output the MFMAs run over the same K
@@ -313,6 +317,9 @@ __global__ void __launch_bounds__(256, 2) k_e_dct_eo(DArgs a) {
   uint16_t* As = reinterpret_cast<uint16_t*>(smem);  // [plane][half][128 x KS]
   uint16_t* Bs = As + NP * 2 * kA;                   // [plane][half][kBW x KS]
   const int nact = a.counts[a.cidx];
+  // the block's first list entry is requested with the list's length
+  const int g_first = a.dact[min((int)blockIdx.x, max(a.dact_cap - 1, 0))];
+  __asm__ volatile("" ::"s"(nact), "s"(g_first));  // both loads issued before the loop test
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const int wr = (w & 1) * 64, hf = w >> 1;
   const int lr = lane & 15, kq = lane >> 4;        // MFMA operand map: row lr, k chunk kq
@@ -320,7 +327,7 @@ __global__ void __launch_bounds__(256, 2) k_e_dct_eo(DArgs a) {
   static_assert(!(SPLIT && (IN16 || OUT16)), "the bf16 split keeps FP32 intermediates");
   const int bseg = tid / NC, bq = tid % NC;         // table staging: segment, 16-byte chunk
   for (int t_ = blockIdx.x; t_ < nact; t_ += gridDim.x) {
-    const int g = a.dact[t_];
+    const int g = t_ == (int)blockIdx.x ? g_first : a.dact[t_];
     if (g < 0) continue;  // padding slot of the XCD-ordered list
     // the tile's record (one load); its first K step is fetched before the
     // map's state is read, so the two round trips overlap
@@ -648,10 +655,13 @@ __global__ void __launch_bounds__(256) k_e_dct_fma(DArgs a) {
   __shared__ T Bs[16][64 + 4];
   __shared__ double red[4];
   const int nact = a.counts[a.cidx];
+  // the block's first list entry is requested with the list's length
+  const int g_first = a.dact[min((int)blockIdx.x, max(a.dact_cap - 1, 0))];
+  __asm__ volatile("" ::"s"(nact), "s"(g_first));  // both loads issued before the loop test
   const int tid = threadIdx.x, tr = tid % 16, tc = tid / 16;
   const int lrow = tid / 4, lk = (tid % 4) * 4;
   for (int t_ = blockIdx.x; t_ < nact; t_ += gridDim.x) {
-    const int g = a.dact[t_];
+    const int g = t_ == (int)blockIdx.x ? g_first : a.dact[t_];
     if (g < 0) continue;  // padding slot of the XCD-ordered list
     const DTile t = dtile(a, g);
     if (!t.ok) continue;
@@ -759,6 +769,7 @@ void e_dct_stage(hipStream_t st, const Engine& e, int ndtiles, int stage, int ex
   a.dtile_map = e.dtile_map;
   // lists: narrow tiles of the two stage parities, then wide tiles
   a.dact = e.dact + ((wide ? 2 : 0) + (stage & 1)) * e.dlist_cap;
+  a.dact_cap = (int)e.dlist_cap;
   a.cidx = (wide ? 4 : 0) + ((stage & 1) ? 3 : 1);
   a.counts = e.counts;
   a.P = e.P;

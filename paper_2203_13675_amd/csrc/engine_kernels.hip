@@ -313,6 +313,7 @@ struct EArgs {
   MapState* ms;
   const int* tile_map;
   const int* act;
+  int act_cap;  // entries of act (its capacity)
   const int* counts;
   double* P;
   long long pstride;
@@ -331,9 +332,16 @@ __device__ __forceinline__ Arrival arrival(const EArgs& A) {
   return Arrival{A.fcnt, A.gcnt, A.gsum, A.gstride, A.P, A.pstride};
 }
 
-#define TILE_LOOP(A)                                                  \
-  const int n_act_ = (A).counts[0];                                   \
+// Grid-stride walk over the active tiles.  The block's first list entry is
+// requested together with the list's length (through an index clamped to
+// the list's capacity; it is used only when the block has a tile), so the
+// walk starts one memory round trip earlier.
+#define TILE_LOOP(A)                                                          \
+  const int n_act_ = (A).counts[0];                                           \
+  const int g_first_ = (A).act[min((int)blockIdx.x, max((A).act_cap - 1, 0))]; \
+  __asm__ volatile("" ::"s"(n_act_), "s"(g_first_)); /* both loads issued here */ \
   for (int t_ = blockIdx.x; t_ < n_act_; t_ += gridDim.x)
+#define TILE_G(A) (t_ == (int)blockIdx.x ? g_first_ : (A).act[t_])
 
 // ---------------------------------------------------------------------------
 // Set-up kernels: wrapped differences, weights, Jacobi diagonal, isolation
@@ -348,7 +356,7 @@ __device__ __forceinline__ double wrap_w(double x) {
 // does not supply one)
 __global__ void __launch_bounds__(64) k_e_wrapdiff(EArgs A, int zero_phi) {
   TILE_LOOP(A) {
-    const int g = A.act[t_];
+    const int g = TILE_G(A);
     const TilePos tp = tile_pos(A.desc, A.tile_map, g);
     const double* psi = A.desc[tp.m].psi;
     double* phi = A.desc[tp.m].phi;
@@ -382,7 +390,7 @@ __global__ void __launch_bounds__(64) k_e_wrapdiff(EArgs A, int zero_phi) {
 __global__ void __launch_bounds__(64) k_e_check(EArgs A, unsigned int* bad) {
   unsigned int b = 0;
   TILE_LOOP(A) {
-    const int g = A.act[t_];
+    const int g = TILE_G(A);
     const TilePos tp = tile_pos(A.desc, A.tile_map, g);
     const double* psi = A.desc[tp.m].psi;
     const float* mask = A.desc[tp.m].mask;
@@ -407,7 +415,7 @@ __device__ __forceinline__ double abs_pow(double r, double e) {
 template <typename T>
 __global__ void __launch_bounds__(64) k_e_weights(EArgs A, double e, double tau) {
   TILE_LOOP(A) {
-    const int g = A.act[t_];
+    const int g = TILE_G(A);
     const TilePos tp = tile_pos(A.desc, A.tile_map, g);
     const MapDesc& d = A.desc[tp.m];
     const double* phi = d.phi;
@@ -460,7 +468,7 @@ __global__ void __launch_bounds__(64) k_e_weights(EArgs A, double e, double tau)
 template <typename T>
 __global__ void __launch_bounds__(64) k_e_diag(EArgs A, int want_inv) {
   TILE_LOOP(A) {
-    const int g = A.act[t_];
+    const int g = TILE_G(A);
     const TilePos tp = tile_pos(A.desc, A.tile_map, g);
     const T* U = cvec<T>(A.U, tp.off);
     const T* V = cvec<T>(A.V, tp.off);
@@ -483,7 +491,7 @@ __global__ void __launch_bounds__(64) k_e_diag(EArgs A, int want_inv) {
 template <typename T>
 __global__ void __launch_bounds__(64) k_e_rhs(EArgs A, int mode) {
   TILE_LOOP(A) {
-    const int g = A.act[t_];
+    const int g = TILE_G(A);
     const TilePos tp = tile_pos(A.desc, A.tile_map, g);
     const MapDesc& d = A.desc[tp.m];
     const T* U = cvec<T>(A.U, tp.off);
@@ -573,7 +581,7 @@ __global__ void __launch_bounds__(64) k_e_rhs(EArgs A, int mode) {
 template <typename T>
 __global__ void __launch_bounds__(64) k_e_pass(EArgs A, int op) {
   TILE_LOOP(A) {
-    const int g = A.act[t_];
+    const int g = TILE_G(A);
     const TilePos tp = tile_pos(A.desc, A.tile_map, g);
     double* phi = A.desc[tp.m].phi;
     double* pp = A.phi_prev + tp.off;
@@ -637,7 +645,7 @@ __global__ void __launch_bounds__(64) k_e_pass(EArgs A, int op) {
 template <typename T, int PC, int CONF>
 __global__ void __launch_bounds__(64) k_e_resid(EArgs A) {
   TILE_LOOP(A) {
-    const int g = A.act[t_];
+    const int g = TILE_G(A);
     const TilePos tp = tile_pos(A.desc, A.tile_map, g);
     const MapState& st = A.ms[tp.m];
     if (st.state != (CONF ? kConfirm : kRun)) continue;
@@ -704,7 +712,7 @@ __global__ void __launch_bounds__(64) k_e_spmv(EArgs A) {
   __shared__ double fred[3];
   __shared__ int fflag;
   TILE_LOOP(A) {
-    const int g = A.act[t_];
+    const int g = TILE_G(A);
     const TilePos tp = tile_pos(A.desc, A.tile_map, g);
     const MapState& st = A.ms[tp.m];
     if (st.state != kRun) continue;
@@ -769,7 +777,7 @@ __global__ void __launch_bounds__(64, 5) k_e_update(EArgs A) {
   __shared__ double fred[3];
   __shared__ int fflag;
   TILE_LOOP(A) {
-    const int g = A.act[t_];
+    const int g = TILE_G(A);
     const TilePos tp = tile_pos(A.desc, A.tile_map, g);
     const MapState& st = A.ms[tp.m];
     if (st.state != kRun) continue;
@@ -887,7 +895,7 @@ __global__ void __launch_bounds__(64, 5) k_e_update(EArgs A) {
 template <typename T>
 __global__ void __launch_bounds__(64) k_e_tc_pivots(EArgs A, int ssor, double omega) {
   TILE_LOOP(A) {
-    const int g = A.act[t_];
+    const int g = TILE_G(A);
     const TilePos tp = tile_pos(A.desc, A.tile_map, g);
     const T* U = cvec<T>(A.U, tp.off);
     const T* V = cvec<T>(A.V, tp.off);
@@ -928,7 +936,7 @@ __global__ void __launch_bounds__(64) k_e_twocolor(EArgs A, T c) {
   __shared__ double fred[3];
   __shared__ int fflag;
   TILE_LOOP(A) {
-    const int g = A.act[t_];
+    const int g = TILE_G(A);
     const TilePos tp = tile_pos(A.desc, A.tile_map, g);
     if (A.ms[tp.m].state != A.expect) continue;
     const T* U = cvec<T>(A.U, tp.off);
@@ -991,7 +999,7 @@ __global__ void __launch_bounds__(64) k_e_twocolor(EArgs A, T c) {
 template <typename T>
 __global__ void __launch_bounds__(64) k_e_apply(EArgs A) {
   TILE_LOOP(A) {
-    const int g = A.act[t_];
+    const int g = TILE_G(A);
     const TilePos tp = tile_pos(A.desc, A.tile_map, g);
     const T* U = cvec<T>(A.U, tp.off);
     const T* V = cvec<T>(A.V, tp.off);
@@ -1036,6 +1044,7 @@ EArgs make_args(const Engine& e) {
   a.ms = e.ms;
   a.tile_map = e.tile_map;
   a.act = e.act;
+  a.act_cap = (int)e.cap_tiles;
   a.counts = e.counts;
   a.P = e.P;
   a.pstride = e.pstride;
