@@ -517,14 +517,14 @@ def test_batch_matches_single(ctx, pc, precision):
 
 
 def test_batch_wide_dct_tiles_match_single(ctx):
-    """A batch with more than 512 narrow even/odd DCT tiles per stage runs the
-    first three DCT stages of its large launches on wide tiles (128 output
-    pairs, among them tiles without a partner: sides 128 and 384), while each
-    map solved alone runs on narrow tiles.  Per output the MFMAs take the same
-    K chunks in the same order, so the results agree bit for bit."""
-    shapes = [(1024, 1024)] * 7 + [(768, 384), (384, 1024), (128, 512), (1024, 768), (512, 1024)]
+    """A batch whose DCT tile lists reach 1024 positions runs the first three
+    even/odd DCT stages of its large launches on wide tiles (128 output pairs,
+    among them tiles without a partner: sides 128 and 384), while each map
+    solved alone runs on narrow tiles.  Per output the MFMAs take the same K
+    chunks in the same order, so the results agree bit for bit."""
+    shapes = [(1024, 1024)] * 16 + [(768, 384), (384, 1024), (128, 512), (1024, 768), (512, 1024)]
     narrow = sum((m // 128) * (n // 128) for m, n in shapes)
-    assert narrow > 512  # the batch's first launches take wide tiles
+    assert narrow >= 1024  # a list holds at least one position per tile
     maps = synth.batch_maps(sides=shapes, seed=91)
     kw = dict(p=0.0, preconditioner="dct", precision="mixed", dct_mode="fp16_scaled", k_max=2,
               outer_tol=0.0)
