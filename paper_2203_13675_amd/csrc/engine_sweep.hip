@@ -40,6 +40,7 @@ struct WArgs {
   const MapDesc* desc;
   MapState* ms;
   const int* mact;
+  int mact_cap;  // entries of mact (its capacity)
   const int* counts;
   double* P;
   long long pstride;
@@ -58,15 +59,27 @@ struct WTile {
   long long off;
 };
 
+// The lookups form a chain of memory round trips ahead of the operands: the
+// active-map count, the block's map, the map's state and its descriptor.
+// The map is requested with the count (through an index clamped to the
+// list's capacity, used only when the slot is active) and the descriptor
+// with the state, so the chain is two round trips instead of four; the
+// empty asm statements keep the compiler from sinking the second load of
+// each pair below the branch that follows.
 template <bool REV>
 __device__ __forceinline__ bool wf_tile(const WArgs& a, WTile& w) {
-  if ((int)blockIdx.y >= a.counts[2]) return false;
-  w.m = a.mact[blockIdx.y];
-  if (a.expect >= 0 && a.ms[w.m].state != a.expect) return false;
-  const MapDesc& d = a.desc[w.m];
+  const int nm = a.counts[2];
+  const int m = a.mact[min((int)blockIdx.y, max(a.mact_cap - 1, 0))];
+  __asm__ volatile("" ::"s"(nm), "s"(m));
+  if ((int)blockIdx.y >= nm) return false;
+  w.m = m;
+  const MapDesc& d = a.desc[m];
   w.M = d.M;
   w.N = d.N;
   w.off = d.off;
+  const int st = a.ms[m].state;
+  __asm__ volatile("" ::"s"(w.M), "s"(w.N), "s"(w.off), "s"(st));
+  if (a.expect >= 0 && st != a.expect) return false;
   const int ty = (d.M + kWT - 1) / kWT;
   w.tx = (d.N + kWT - 1) / kWT;
   if (a.diag >= ty + w.tx - 1) return false;
@@ -548,6 +561,7 @@ static WArgs make_wargs(const Engine& e, int expect, bool ssor, double omega, co
   a.desc = e.desc;
   a.ms = e.ms;
   a.mact = e.mact;
+  a.mact_cap = e.cap_maps;
   a.counts = e.counts;
   a.P = e.P;
   a.pstride = e.pstride;
