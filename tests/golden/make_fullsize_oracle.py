@@ -66,7 +66,7 @@ def cases():
     # peaks1024: each preconditioner, p in {0, 1}
     for p in (0, 1):
         out.append(_case("peaks1024_exact_p%d" % p, "peaks1024", "exact", p=p))
-        for pc in ("dct", "jacobi", "ilu0"):
+        for pc in ("dct", "jacobi", "ilu0", "none", "ic0", "ssor"):
             base = "peaks1024_same_%s_p%d" % (pc, p)
             out.append(_case(base, "peaks1024", "same", p=p, pc=pc))
             for s in range(3):

@@ -8,8 +8,9 @@ mean over the valid pixels removed (the solution is unique up to a constant),
 on the whole grid at 1024^2 and on the strided sample the cache keeps at
 2048^2 (every 2nd pixel) and 4096^2 (every 4th).
 
-* FP64 path, 1024^2 peaks, p in {0, 1}, DCT / Jacobi / ILU(0), ten outer
-  iterations with the relative-residual stop rule: the oracle running the same
+* FP64 path, 1024^2 peaks, p in {0, 1}, the paper's five preconditioners
+  (none, Jacobi, ILU(0), IC(0), SSOR) and the DCT one, ten outer iterations
+  with the relative-residual stop rule: the oracle running the same
   algorithm.  Bound: 50 x the distance the oracle's own answer moves under a
   1e-14 relative perturbation of psi (the stop test can fall one iteration
   apart under different rounding), at least 1e-6 rad; inner iteration totals
@@ -113,7 +114,7 @@ def sensitivity(base):
 # ---------------------------------------------------------------------------
 # 1024 x 1024 peaks: FP64 path against the oracle's same algorithm
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("pc", ["dct", "jacobi", "ilu0"])
+@pytest.mark.parametrize("pc", ["dct", "jacobi", "ilu0", "none", "ic0", "ssor"])
 @pytest.mark.parametrize("p", [0, 1])
 def test_peaks1024_fp64_matches_oracle(ctx, oracle, pc, p):
     base = "peaks1024_same_%s_p%d" % (pc, p)
