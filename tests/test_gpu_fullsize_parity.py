@@ -154,7 +154,9 @@ def test_peaks1024_fp64_fixed_work(ctx, oracle, pc):
 # 1024 x 1024 peaks: mixed path against exact inner solves
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("pc,mode", [("dct", "split_bf16"), ("dct", "fp16_scaled"),
-                                     ("jacobi", "split_bf16"), ("ilu0", "split_bf16")])
+                                     ("jacobi", "split_bf16"), ("ilu0", "split_bf16"),
+                                     ("none", "split_bf16"), ("ic0", "split_bf16"),
+                                     ("ssor", "split_bf16")])
 @pytest.mark.parametrize("p", [0, 1])
 def test_peaks1024_mixed_vs_exact(ctx, oracle, pc, mode, p):
     ex = Cached("peaks1024_exact_p%d" % p)
