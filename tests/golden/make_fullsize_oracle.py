@@ -33,7 +33,7 @@ counts, outer errors and final inner residuals, and the settings.
 Workloads (``synth``): peaks1024 (1024^2 peaks, 60 rad, noise 0.5),
 gauss2048_hole (2048^2, 20 Gaussians, noise 0.8, 10 % zero-quality hole),
 ramp4096 (4096^2 peaks + 120 rad ramp, noise 0.5), and one square map of each
-side length of the 256-map batch.
+side length of the 256-map batch and five rectangular ones.
 """
 from __future__ import annotations
 
@@ -50,6 +50,9 @@ CACHE = os.path.join(HERE, "fullsize_cache")
 # one square map of each side length of the benchmark batch (indices into
 # synth.batch_maps(256, 3000)): sides 128, 256, 384, 512, 768, 1024
 BATCH_REPS = {128: 33, 256: 7, 384: 19, 512: 105, 768: 23, 1024: 22}
+# and rectangular maps of the batch (the two DCT stage parities contract
+# different lengths; sides 128 and 384 on one axis only)
+BATCH_RECT = {(128, 1024): 4, (1024, 128): 52, (384, 768): 1, (768, 384): 119, (1024, 384): 31}
 EXACT_TOL = 1e-12      # 1e-11 for the 4096^2 map (FP64 rounding floor of its residual)
 EXACT_LMAX = 4000
 TOL_SWEEP = (1e-7, 1e-8, 1e-9)
@@ -84,7 +87,7 @@ def cases():
             out.append(_case("%s_exact_k%d" % (w, k), w, "exact", k_max=k, stride=st))
             out.append(_case("%s_same_k%d" % (w, k), w, "same", k_max=k, stride=st))
     # one square map per side length of the batch
-    for side, k in BATCH_REPS.items():
+    for k in list(BATCH_REPS.values()) + list(BATCH_RECT.values()):
         w = "batch256:%d" % k
         out.append(_case("batch256_map%d_exact" % k, w, "exact"))
         out.append(_case("batch256_map%d_same" % k, w, "same"))

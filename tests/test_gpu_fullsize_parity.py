@@ -22,8 +22,9 @@ on the whole grid at 1024^2 and on the strided sample the cache keeps at
   max(3 x the error the FP64 oracle makes at the same tolerance, 1e-4 rad);
   at 1024^2 also at the inner tolerance where the FP64 oracle itself is well
   inside 1e-4 rad, held to 1e-4 rad.
-* The 256-map batch: one square map of each side length against exact inner
-  solves over ten outer iterations (same bound), and every map's residual after
+* The 256-map batch: one square map of each side length and five
+  rectangular ones against exact inner solves over ten outer iterations
+  (same bound), and every map's residual after
   one outer step assembled by the oracle.
 """
 import json
@@ -43,6 +44,7 @@ CACHE = os.path.join(HERE, "golden", "fullsize_cache")
 TOL = 1e-6
 TARGET_RAD = 1e-4
 BATCH_REPS = {128: 33, 256: 7, 384: 19, 512: 105, 768: 23, 1024: 22}
+BATCH_RECT = {(128, 1024): 4, (1024, 128): 52, (384, 768): 1, (768, 384): 119, (1024, 384): 31}
 
 
 @pytest.fixture(scope="module")
@@ -222,21 +224,22 @@ def test_large_maps_vs_exact(ctx, oracle, workload, mode, k, precision):
 # The 256-map batch
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("mode", ["fp16_scaled", "split_bf16"])
-def test_batch256_square_maps_vs_exact(ctx, oracle, mode):
+def test_batch256_maps_vs_exact(ctx, oracle, mode):
     maps = synth.batch_maps(256, seed=3000)
     psis = [dev(p) for p, _ in maps]
     phis, rc, stats = ctx.batch(psis, p=0.0, eps=0.01, preconditioner="dct", tol=TOL,
                                 precision="mixed", dct_mode=mode, k_max=10, outer_tol=0.0)
     assert rc in (0, 1)
-    for side, k in BATCH_REPS.items():
+    reps = [((side, side), k) for side, k in BATCH_REPS.items()] + list(BATCH_RECT.items())
+    for shape, k in reps:
         ex = Cached("batch256_map%d_exact" % k)
         same = Cached("batch256_map%d_same" % k)
         d_orc = same.dist(ex)
         psi = maps[k][0]
-        assert psi.shape == (side, side)
+        assert psi.shape == shape
         d = ex.compare(host(phis[k]), valid_pixels(oracle, psi, None))
         print("batch256 %s map %d (%dx%d): max |phi - exact| %.3e, FP64 oracle at the same "
-              "tolerance %.3e; inner %d" % (mode, k, side, side, d, d_orc,
+              "tolerance %.3e; inner %d" % (mode, k, shape[0], shape[1], d, d_orc,
                                              stats[k]["inner_iters_total"]))
         assert stats[k]["final_relres"] <= TOL
         assert d <= max(3.0 * d_orc, TARGET_RAD)
